@@ -1,0 +1,358 @@
+"""Seeded synthetic local-bundle-adjustment windows.
+
+This module only *generates inputs*: camera trajectories, 3-D points, visibility-based
+associations, octaves, pixel noise, injected outliers and initial perturbations.  It holds
+none of the solver's arithmetic (no information weighting, robust kernel, Jacobians,
+normal equations or damping).  To synthesise measurements it projects the noise-free
+points with its own pinhole model, and it builds rotations and the initial pose
+perturbation with SciPy's ``expm``.  Both the CPU oracle and the GPU path
+consume its output; it imports neither.
+
+The windows stand in for the stereo-inertial local maps of EuRoC / TUM-VI that the paper
+evaluates on (Section V, Experimental Setup): keyframes carrying hundreds to thousands of
+features, local maps with thousands to tens of thousands of points (Section IV-A).
+
+Camera: pinhole 752x480, fx=fy=458, cx=367, cy=248, no distortion, frame x right / y down
+/ z forward; stereo baseline 0.11 m (bf = 50.38 px*m).  Observation noise on u, v, uR is
+N(0, (1.2^o)^2) for octave o ~ U{0..7}; exactly round(0.05 N) observations are replaced by
+uniform outliers; optimisable keyframes start at Exp(w, v) * T_true with per-axis
+w ~ N(0, 0.5 deg), v ~ N(0, 2 cm), points at X_true + N(0, 5 cm).
+
+Draw order inside one window (one ``numpy.random.Generator``): trajectory, points
+(rejection batches), octaves, stereo choice, pixel noise, outlier indices, outlier values,
+pose perturbations, point perturbations.  Multi-window configurations draw each window
+from ``SeedSequence(seed).spawn(n)``; a window's own size parameters come first.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from scipy.linalg import expm
+
+FX = FY = 458.0
+CX, CY = 367.0, 248.0
+WIDTH, HEIGHT = 752, 480
+BASELINE_M = 0.11
+BF = BASELINE_M * FX
+N_LEVELS = 8
+SCALE_FACTOR = 1.2
+MIN_DEPTH_VIS = 0.1
+HUBER2_MONO = 5.991
+HUBER2_STEREO = 7.815
+
+CAM = np.array([FX, FY, CX, CY, BF], dtype=np.float64)
+SIGMA2 = np.array([SCALE_FACTOR ** (2 * o) for o in range(N_LEVELS)], dtype=np.float64)
+
+
+# ----------------------------------------------------------------------------------------
+# geometry helpers (generation only)
+# ----------------------------------------------------------------------------------------
+def _look_rotation(z_axis: np.ndarray) -> np.ndarray:
+    """Camera-to-world rotation whose optical axis is ``z_axis`` and whose y axis points
+    as close to world +y (down) as possible."""
+    z = z_axis / np.linalg.norm(z_axis)
+    x = np.cross(np.array([0.0, 1.0, 0.0]), z)
+    x /= np.linalg.norm(x)
+    y = np.cross(z, x)
+    return np.stack([x, y, z], axis=1)
+
+
+def _pose_from_center(R_wc: np.ndarray, c: np.ndarray) -> np.ndarray:
+    R_cw = R_wc.T
+    t_cw = -R_cw @ c
+    return np.concatenate([R_cw, t_cw[:, None]], axis=1)
+
+
+def _twist_exp(w: np.ndarray, v: np.ndarray) -> np.ndarray:
+    """4x4 matrix exponential of the twist (rotation w, translation v) via SciPy."""
+    A = np.zeros((4, 4))
+    A[0, 1], A[0, 2], A[1, 2] = -w[2], w[1], -w[0]
+    A[1, 0], A[2, 0], A[2, 1] = w[2], -w[1], w[0]
+    A[:3, 3] = v
+    return expm(A)
+
+
+def _project(T: np.ndarray, X: np.ndarray):
+    """Noise-free pinhole projection of points X (M,3) into poses T (K,3,4).
+
+    Returns camera-frame depth (M,K), u, v, uR (M,K)."""
+    R = T[:, :, :3]
+    t = T[:, :, 3]
+    Xc = np.einsum("kij,mj->mki", R, X) + t[None, :, :]
+    z = Xc[..., 2]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        u = FX * Xc[..., 0] / z + CX
+        v = FY * Xc[..., 1] / z + CY
+        ur = u - BF / z
+    return z, u, v, ur
+
+
+def _visible(z, u, v):
+    return (z > MIN_DEPTH_VIS) & (u >= 0) & (u < WIDTH) & (v >= 0) & (v < HEIGHT)
+
+
+# ----------------------------------------------------------------------------------------
+# trajectories
+# ----------------------------------------------------------------------------------------
+def _arc_trajectory(K: int) -> tuple[np.ndarray, np.ndarray]:
+    """K keyframes on a radius-2 m circle, evenly spaced over 1 rad (arc length 2 m),
+    optical axis horizontal and pointing at the circle centre."""
+    phis = np.linspace(-0.5, 0.5, K)
+    poses, centers = [], []
+    for phi in phis:
+        c = np.array([2.0 * math.sin(phi), 0.0, -2.0 * math.cos(phi)])
+        R_wc = _look_rotation(-c)
+        poses.append(_pose_from_center(R_wc, c))
+        centers.append(c)
+    return np.array(poses), np.array(centers)
+
+
+def _walk_trajectory(rng: np.random.Generator, K: int, length: float):
+    """K keyframes along a random walk of the given length: heading yaw / pitch random
+    walks N(0, 10 deg) / N(0, 2 deg) per step, look direction = heading yaw + N(0, 5 deg)."""
+    step = length / max(K - 1, 1)
+    yaw = pitch = 0.0
+    p = np.zeros(3)
+    poses, centers = [], []
+    d2r = math.pi / 180.0
+    for i in range(K):
+        if i > 0:
+            yaw += rng.normal(0.0, 10.0 * d2r)
+            pitch += rng.normal(0.0, 2.0 * d2r)
+            p = p + step * np.array([math.sin(yaw) * math.cos(pitch), -math.sin(pitch),
+                                     math.cos(yaw) * math.cos(pitch)])
+        look_yaw = yaw + rng.normal(0.0, 5.0 * d2r)
+        d = np.array([math.sin(look_yaw) * math.cos(pitch), -math.sin(pitch),
+                      math.cos(look_yaw) * math.cos(pitch)])
+        poses.append(_pose_from_center(_look_rotation(d), p.copy()))
+        centers.append(p.copy())
+    return np.array(poses), np.array(centers)
+
+
+# ----------------------------------------------------------------------------------------
+# one window
+# ----------------------------------------------------------------------------------------
+def make_window(rng: np.random.Generator, *, trajectory: str, K: int, n_fixed: int, M: int,
+                nobs: tuple[int, int], stereo_p: float, walk_length: float = 6.0,
+                depth: tuple[float, float] = (1.0, 12.0), noise: bool = True,
+                outlier_frac: float = 0.05) -> dict:
+    """Build one window.  ``nobs=(lo, hi)`` draws each point's wanted observation count
+    from U{lo..hi} (lo == hi for a fixed count); it is capped by visibility."""
+    if trajectory == "arc":
+        T_true, centers = _arc_trajectory(K)
+    else:
+        T_true, centers = _walk_trajectory(rng, K, walk_length)
+
+    # --- points, redrawn until each is visible in >= 2 keyframes -----------------------
+    pts = []
+    have = 0
+    while have < M:
+        need = M - have
+        nb = need + need // 4 + 16
+        if trajectory == "arc":
+            lo = np.array([-1.5, -1.0, 2.0])
+            hi = np.array([1.5, 1.0, 8.0])
+            P_c = rng.uniform(lo, hi, size=(nb, 3))
+            mid = K // 2
+            R_wc = T_true[mid, :, :3].T
+            c = centers[mid]
+            cand = P_c @ R_wc.T + c
+        else:
+            anchor = rng.integers(0, K, size=nb)
+            uu = rng.uniform(0.0, WIDTH, size=nb)
+            vv = rng.uniform(0.0, HEIGHT, size=nb)
+            dd = rng.uniform(depth[0], depth[1], size=nb)
+            P_c = np.stack([(uu - CX) / FX * dd, (vv - CY) / FY * dd, dd], axis=1)
+            R_wc = np.transpose(T_true[anchor, :, :3], (0, 2, 1))
+            cand = np.einsum("nij,nj->ni", R_wc, P_c) + centers[anchor]
+        z, u, v, _ = _project(T_true, cand)
+        ok = _visible(z, u, v).sum(axis=1) >= 2
+        cand = cand[ok][:need]
+        pts.append(cand)
+        have += len(cand)
+    X_true = np.concatenate(pts, axis=0)[:M]
+
+    # --- association: each point seen by its n nearest visible keyframes ---------------
+    z, u, v, ur = _project(T_true, X_true)
+    vis = _visible(z, u, v)
+    dist = np.linalg.norm(X_true[:, None, :] - centers[None, :, :], axis=2)
+    dist = np.where(vis, dist, np.inf)
+    order = np.argsort(dist, axis=1, kind="stable")
+    if nobs[0] == nobs[1]:
+        want = np.full(M, nobs[0])
+    else:
+        want = rng.integers(nobs[0], nobs[1] + 1, size=M)
+    take = np.minimum(want, vis.sum(axis=1))
+    sel = np.arange(K)[None, :] < take[:, None]
+    pt_idx = np.repeat(np.arange(M), K).reshape(M, K)[sel]
+    kf_idx = order[sel]
+    # sort by point, then keyframe
+    srt = np.lexsort((kf_idx, pt_idx))
+    pt_idx = pt_idx[srt].astype(np.int32)
+    kf_idx = kf_idx[srt].astype(np.int32)
+    N = len(pt_idx)
+    zz = z[pt_idx, kf_idx]
+    u0 = u[pt_idx, kf_idx]
+    v0 = v[pt_idx, kf_idx]
+    ur0 = ur[pt_idx, kf_idx]
+
+    # --- octaves, stereo choice, noise --------------------------------------------------
+    octv = rng.integers(0, N_LEVELS, size=N).astype(np.uint8)
+    stereo_ok = ur0 >= 0.0
+    is_stereo = (rng.uniform(size=N) < stereo_p) & stereo_ok
+    sig = SCALE_FACTOR ** octv.astype(np.float64)
+    nz = rng.normal(size=(3, N)) * sig[None, :]
+    if not noise:
+        nz[:] = 0.0
+    obs_z = np.empty((3, N))
+    obs_z[0] = u0 + nz[0]
+    obs_z[1] = v0 + nz[1]
+    obs_z[2] = np.where(is_stereo, ur0 + nz[2], -1.0)
+
+    # --- outliers ------------------------------------------------------------------------
+    is_out = np.zeros(N, dtype=bool)
+    n_out = int(round(outlier_frac * N)) if noise else 0
+    if n_out > 0:
+        idx = rng.choice(N, size=n_out, replace=False)
+        uo = rng.uniform(0.0, WIDTH, size=n_out)
+        vo = rng.uniform(0.0, HEIGHT, size=n_out)
+        do = rng.uniform(0.0, BF / depth[0], size=n_out)
+        obs_z[0, idx] = uo
+        obs_z[1, idx] = vo
+        obs_z[2, idx] = np.where(is_stereo[idx], uo - do, -1.0)
+        is_out[idx] = True
+
+    # --- initial perturbation ------------------------------------------------------------
+    fixed = np.zeros(K, dtype=np.uint8)
+    fixed[:n_fixed] = 1
+    T_init = T_true.copy()
+    d2r = math.pi / 180.0
+    for k in range(K):
+        if fixed[k]:
+            continue
+        w = rng.normal(0.0, 0.5 * d2r, size=3)
+        vv = rng.normal(0.0, 0.02, size=3)
+        E = _twist_exp(w, vv)
+        T4 = np.vstack([T_true[k], [0, 0, 0, 1]])
+        T_init[k] = (E @ T4)[:3]
+    X_init = X_true + rng.normal(0.0, 0.05, size=X_true.shape)
+
+    return {
+        "T_cw": T_init.reshape(K, 12).copy(),
+        "T_true": T_true.reshape(K, 12).copy(),
+        "fixed": fixed,
+        "X": X_init,
+        "X_true": X_true,
+        "obs_kf": kf_idx,
+        "obs_pt": pt_idx,
+        "obs_z": np.ascontiguousarray(obs_z),
+        "obs_type": is_stereo.astype(np.uint8),
+        "obs_oct": octv,
+        "sigma2": SIGMA2.copy(),
+        "cam": CAM.copy(),
+        "is_outlier_true": is_out,
+    }
+
+
+# ----------------------------------------------------------------------------------------
+# the five workload configurations
+# ----------------------------------------------------------------------------------------
+def c1_mono(seed: int = 0, noise: bool = True) -> dict:
+    """Monocular window: 10 optimisable + 5 fixed keyframes on a 2 m arc, 1,500 points in
+    a box 2-8 m deep, each seen by its 8 nearest visible keyframes (about 12k obs)."""
+    rng = np.random.default_rng(seed)
+    return make_window(rng, trajectory="arc", K=15, n_fixed=5, M=1500, nobs=(8, 8),
+                       stereo_p=0.0, depth=(2.0, 8.0), noise=noise)
+
+
+def c2_stereo(seed: int = 1, noise: bool = True) -> dict:
+    """Stereo window: 20 optimisable + 10 fixed keyframes on a 6 m random walk, 8,000
+    points 1-12 m deep, 8 observations per point (about 60k obs, 70% stereo)."""
+    rng = np.random.default_rng(seed)
+    return make_window(rng, trajectory="walk", K=30, n_fixed=10, M=8000, nobs=(8, 8),
+                       stereo_p=0.7, walk_length=6.0, noise=noise)
+
+
+def c3_precision(seed: int = 2, noise: bool = True) -> dict:
+    """Large stereo window: 30 optimisable + 20 fixed keyframes over 10 m, 20,000 points,
+    10 observations per point (about 200k obs)."""
+    rng = np.random.default_rng(seed)
+    return make_window(rng, trajectory="walk", K=50, n_fixed=20, M=20000, nobs=(10, 10),
+                       stereo_p=0.7, walk_length=10.0, noise=noise)
+
+
+def c4_windows(seed: int = 3, n_windows: int = 64, noise: bool = True) -> list[dict]:
+    """64 windows of 10 keyframes (2 m walk) and 2,000 points, 8 obs per point; even
+    windows monocular, odd windows 70/30 stereo/mono."""
+    out = []
+    for i, ss in enumerate(np.random.SeedSequence(seed).spawn(n_windows)):
+        rng = np.random.default_rng(ss)
+        out.append(make_window(rng, trajectory="walk", K=10, n_fixed=3, M=2000, nobs=(8, 8),
+                               stereo_p=0.0 if i % 2 == 0 else 0.7, walk_length=2.0,
+                               noise=noise))
+    return out
+
+
+def c5_window_sizes(seed: int = 4, n_windows: int = 256) -> list[tuple[int, int]]:
+    """(K, M) of each batched window, drawn first from that window's own stream."""
+    sizes = []
+    for ss in np.random.SeedSequence(seed).spawn(n_windows):
+        rng = np.random.default_rng(ss)
+        sizes.append((int(rng.integers(5, 41)), int(rng.integers(500, 20001))))
+    return sizes
+
+
+def c5_windows(seed: int = 4, n_windows: int = 256, noise: bool = True,
+               only: list[int] | None = None, max_points: int | None = None) -> list[dict]:
+    """Batched windows: K ~ U{5..40} with floor(K/3) fixed, walk of 0.2 K m, points
+    M ~ U{500..20,000}, 4-10 observations per point, 70/30 stereo/mono.  ``only`` builds
+    a subset of the windows (same streams, so the same content); ``max_points`` caps M
+    (smaller test batches with the same structure)."""
+    out = []
+    for i, ss in enumerate(np.random.SeedSequence(seed).spawn(n_windows)):
+        if only is not None and i not in only:
+            continue
+        rng = np.random.default_rng(ss)
+        K = int(rng.integers(5, 41))
+        M = int(rng.integers(500, 20001))
+        if max_points is not None:
+            M = min(M, max_points)
+        out.append(make_window(rng, trajectory="walk", K=K, n_fixed=K // 3, M=M, nobs=(4, 10),
+                               stereo_p=0.7, walk_length=0.2 * K, noise=noise))
+    return out
+
+
+def tiny_window(seed: int, K: int = 4, n_fixed: int = 1, M: int = 20, stereo_p: float = 0.5,
+                noise: bool = True, nobs: tuple[int, int] = (2, 4), outlier_frac: float = 0.05) -> dict:
+    """Small window for brute-force checks (dense normal equations, finite differences)."""
+    rng = np.random.default_rng(seed)
+    return make_window(rng, trajectory="walk", K=K, n_fixed=n_fixed, M=M, nobs=nobs,
+                       stereo_p=stereo_p, walk_length=0.3 * K, noise=noise,
+                       outlier_frac=outlier_frac)
+
+
+def concat(windows: list[dict]) -> dict:
+    """Concatenate windows into one batch: arrays end to end, observation indices stay
+    window-local, offsets give each window's keyframe / point / observation range."""
+    kf_off = np.zeros(len(windows) + 1, dtype=np.int64)
+    pt_off = np.zeros(len(windows) + 1, dtype=np.int64)
+    ob_off = np.zeros(len(windows) + 1, dtype=np.int64)
+    for i, w in enumerate(windows):
+        kf_off[i + 1] = kf_off[i] + len(w["fixed"])
+        pt_off[i + 1] = pt_off[i] + len(w["X"])
+        ob_off[i + 1] = ob_off[i] + len(w["obs_kf"])
+    cat = {
+        "T_cw": np.concatenate([w["T_cw"] for w in windows]),
+        "fixed": np.concatenate([w["fixed"] for w in windows]),
+        "X": np.concatenate([w["X"] for w in windows]),
+        "obs_kf": np.concatenate([w["obs_kf"] for w in windows]),
+        "obs_pt": np.concatenate([w["obs_pt"] for w in windows]),
+        "obs_z": np.concatenate([w["obs_z"] for w in windows], axis=1),
+        "obs_type": np.concatenate([w["obs_type"] for w in windows]),
+        "obs_oct": np.concatenate([w["obs_oct"] for w in windows]),
+        "sigma2": windows[0]["sigma2"],
+        "cam": windows[0]["cam"],
+        "kf_off": kf_off, "pt_off": pt_off, "obs_off": ob_off,
+    }
+    return cat
