@@ -1,0 +1,207 @@
+/*
+ * lba.h -- C ABI of the MI355X (gfx950) Local Bundle Adjustment library (liblba.so).
+ *
+ * The operation (paper Section III-C "Local Bundle Adjustment", Section IV-E "Local
+ * Bundle Adjustment"): refine the poses of a window of local keyframes and the 3-D
+ * points they observe by nonlinear least squares on the reprojection residuals, solved
+ * iteratively by Levenberg-Marquardt with the points eliminated by the Schur
+ * complement (the reduced camera system is factorised, the points back-substituted).
+ *
+ * Formulation (the library's reading of that passage; every symbol below is fixed):
+ *   residual   e = z - pi(T_k X_j): mono (u, v), stereo (u, v, uR) with
+ *              pi = (fx x/z + cx, fy y/z + cy, fx x/z + cx - bf/z), X_c = R X + t;
+ *   weight     s = |e|^2 / sigma2[octave];  robust cost rho(s) = s for s <= d2, else
+ *              2 sqrt(d2 s) - d2 (Huber on s; d2 = huber2_mono / huber2_stereo);
+ *   cost       F = sum over active observations of rho(s);
+ *   step       (H + lambda I) d = b, H = sum w J^T Om J, b = sum w J^T Om e, w = rho'(s),
+ *              Om = I / sigma2, J the Jacobian of pi; poses move on the left,
+ *              T <- Exp(dxi) T with the twist ordered (rotation, translation);
+ *   damping    lambda0 = tau * max diag(H) at the start of each round; gain ratio
+ *              (F - F') / (d^T (lambda d + b)); accept iff > 0 and finite, then
+ *              lambda *= max(1/3, 1 - (2 g - 1)^3); otherwise lambda *= nu, nu *= 2;
+ *              max_trials consecutive rejections end a round;
+ *   schedule   round 1 on all observations (iters_round1 iterations); an observation
+ *              is an outlier if s > chi2(type) or its depth <= 0; round 2 on the
+ *              inliers (iters_round2 iterations, lambda re-initialised); the returned
+ *              flags are recomputed on all observations at the final state.
+ *
+ * Memory: every array is caller-owned.  Arrays marked DEVICE live in device memory of
+ * the context's GPU (e.g. torch tensors); arrays marked HOST are small plan metadata in
+ * host memory.  All device work is enqueued on the caller's HIP stream; the solve
+ * synchronises that stream a few times to read per-window completion flags (see
+ * lba_solve).  No entry point throws; every failure is a status code, and
+ * lba_last_error() gives a message.  A context is not thread-safe: use one per thread.
+ */
+#ifndef LBA_H
+#define LBA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBA_ABI_VERSION 1
+
+typedef enum {
+    LBA_OK = 0,
+    LBA_ERR_INVALID_ARGUMENT = -1,   /* bad pointer, size, index, octave, flag, ...      */
+    LBA_ERR_OUT_OF_MEMORY = -2,      /* a host allocation of the context failed          */
+    LBA_ERR_HIP = -3,                /* a HIP runtime call failed (message has the text) */
+    LBA_ERR_WORKSPACE_TOO_SMALL = -4,
+    LBA_ERR_UNSUPPORTED = -5         /* a window exceeds the built limits (see below)    */
+} lba_status;
+
+typedef enum {
+    LBA_PREC_FP64 = 0,   /* everything in FP64 */
+    LBA_PREC_MIXED = 1   /* Jacobians, Hessian blocks and Schur complement in FP32 with FP32
+                            accumulation; residuals, cost, gain ratio, damping, states and
+                            the reduced-camera-system Cholesky in FP64 */
+} lba_precision;
+
+/* Solver options.  lba_default_options() fills the values noted in brackets. */
+typedef struct {
+    int32_t precision;       /* lba_precision [LBA_PREC_FP64] */
+    int32_t iters_round1;    /* LM iterations before the outlier pass [5] */
+    int32_t iters_round2;    /* LM iterations after it [10] */
+    int32_t max_trials;      /* damped solves per iteration before the round ends [10] */
+    int32_t round2_robust;   /* 1: keep the Huber kernel in round 2, 0: plain squares [1] */
+    int32_t check_inputs;    /* 1: validate indices/octaves/sortedness on the GPU first [1] */
+    double huber2_mono;      /* Huber threshold on s, monocular [5.991] */
+    double huber2_stereo;    /* Huber threshold on s, stereo [7.815] */
+    double chi2_mono;        /* outlier threshold on s, monocular [5.991] */
+    double chi2_stereo;      /* outlier threshold on s, stereo [7.815] */
+    double tau;              /* initial damping factor [1e-5] */
+    int32_t points_per_tile; /* 0: chosen by the library's tile tuner; else fixed */
+    int32_t reserved;
+} lba_options;
+
+typedef struct {
+    double fx, fy, cx, cy;   /* pinhole intrinsics, pixels */
+    double bf;               /* stereo baseline times fx (px*m); only read for stereo obs */
+} lba_intrinsics;
+
+/*
+ * One window, or a batch of windows concatenated end to end (lba_solve_batch).
+ * Observation indices are local to their window: obs_kf in [0, window's n_kf),
+ * obs_pt in [0, window's n_pt), and within a window obs_pt must be non-decreasing
+ * (observations grouped by point).  A point may have at most 64 observations.
+ */
+typedef struct {
+    int32_t n_kf, n_pt, n_obs;   /* totals over the batch */
+    int32_t n_levels;            /* entries of sigma2, 1..32 */
+    const double *T_cw;          /* DEVICE n_kf x 12, row-major [R | t], world -> camera */
+    const uint8_t *fixed;        /* HOST   n_kf, 1 = pose held fixed (decides the size of the
+                                    reduced system, hence the launch plan) */
+    const double *X_w;           /* DEVICE n_pt x 3 */
+    const int32_t *obs_kf;       /* DEVICE n_obs */
+    const int32_t *obs_pt;       /* DEVICE n_obs */
+    const void *obs_z;           /* DEVICE 3 x n_obs planar: u[n_obs], v[n_obs], uR[n_obs] */
+    int32_t obs_z_f32;           /* 0: obs_z is double, 1: float */
+    int32_t reserved;
+    const uint8_t *obs_type;     /* DEVICE n_obs, 0 mono / 1 stereo */
+    const uint8_t *obs_oct;      /* DEVICE n_obs, octave < n_levels */
+    const double *sigma2;        /* HOST   n_levels, measurement variance per octave (px^2) */
+    lba_intrinsics cam;
+} lba_problem;
+
+/* Window boundaries of a batch: HOST arrays of n_windows + 1 offsets into the
+ * concatenated keyframe / point / observation arrays (first 0, last the totals). */
+typedef struct {
+    int32_t n_windows;
+    int32_t reserved;
+    const int32_t *kf_off;
+    const int32_t *pt_off;
+    const int32_t *obs_off;
+} lba_batch;
+
+/* Per-window statistics row (doubles) written to lba_result.stats when it is not NULL */
+enum {
+    LBA_STAT_F_INITIAL = 0,   /* round-1 cost at the input state */
+    LBA_STAT_F_FINAL = 1,     /* round-2 cost at the returned state */
+    LBA_STAT_ITERS_R1 = 2,    /* accepted iterations, round 1 */
+    LBA_STAT_ITERS_R2 = 3,    /* accepted iterations, round 2 */
+    LBA_STAT_TRIALS = 4,      /* damped solves, both rounds */
+    LBA_STAT_LAMBDA = 5,      /* damping at the end */
+    LBA_STAT_TERM_R1 = 6,     /* 1 if round 1 ended on max_trials rejections */
+    LBA_STAT_TERM_R2 = 7,
+    LBA_STAT_N_OUTLIERS = 8,  /* returned flags set */
+    LBA_STAT_F_END_R1 = 9,    /* round-1 cost at the end of round 1 */
+    LBA_STAT_F_START_R2 = 10, /* round-2 cost at the start of round 2 */
+    LBA_STAT_KOPT = 11,       /* optimisable keyframes */
+    LBA_STATS_LEN = 12
+};
+
+typedef struct {
+    double *T_out;       /* DEVICE n_kf x 12; may alias lba_problem.T_cw */
+    double *X_out;       /* DEVICE n_pt x 3;  may alias lba_problem.X_w */
+    uint8_t *outlier;    /* DEVICE n_obs, 1 = outlier at the final state */
+    double *stats;       /* HOST n_windows x LBA_STATS_LEN, or NULL */
+} lba_result;
+
+typedef struct lba_ctx lba_ctx;
+
+int32_t lba_abi_version(void);
+const char *lba_status_string(lba_status status);
+void lba_default_options(lba_options *opt);
+
+/* Create a context bound to HIP device `device`.  Options are copied. */
+lba_status lba_create(const lba_options *opt, int32_t device, lba_ctx **out);
+/* Destroy a context (NULL-safe).  Waits for nothing; the caller orders it after its
+ * last solve on the stream. */
+void lba_destroy(lba_ctx *ctx);
+/* Message of the last failure on this context ("" if none). */
+const char *lba_last_error(const lba_ctx *ctx);
+/* Replace the options of a context. */
+lba_status lba_set_options(lba_ctx *ctx, const lba_options *opt);
+
+/* Bytes of DEVICE workspace lba_solve / lba_solve_batch need for this problem
+ * (batch NULL: one window).  Limits: per window n_kf <= 128, optimisable keyframes
+ * <= 30 (FP64) or <= 40 (mixed), at most 64 observations per point; beyond them the
+ * call returns LBA_ERR_UNSUPPORTED. */
+lba_status lba_workspace_size(lba_ctx *ctx, const lba_problem *problem, const lba_batch *batch,
+                              size_t *bytes);
+
+/* Solve one window.  `workspace` is DEVICE memory of at least lba_workspace_size bytes,
+ * aligned to 256 bytes; `stream` is a hipStream_t (NULL: the null stream).  The stream is
+ * synchronised after input validation, about twice per LM round to read completion
+ * flags, and at the end; the results are complete when the call returns LBA_OK. */
+lba_status lba_solve(lba_ctx *ctx, const lba_problem *problem, lba_result *result,
+                     void *workspace, size_t workspace_bytes, void *stream);
+
+/* Solve many independent windows together: every kernel of an LM step covers all of
+ * them in one launch, so windows of uneven size share the GPU.  Each window follows
+ * exactly the schedule lba_solve gives it alone. */
+lba_status lba_solve_batch(lba_ctx *ctx, const lba_problem *problem, const lba_batch *batch,
+                           lba_result *result, void *workspace, size_t workspace_bytes,
+                           void *stream);
+
+/* ---- per-kernel timing ------------------------------------------------------------------
+ * With profiling enabled, every kernel a solve launches is bracketed by two HIP events on
+ * the caller's stream and, at the end of the solve, its duration is added to the counters
+ * of its kernel class.  Enabling resets the counters.  Reading returns the number of
+ * launches and their summed duration in milliseconds for one class. */
+typedef enum {
+    LBA_KCLASS_LINEARIZE = 0,    /* residual + Jacobian + Hessian blocks + Schur, per step */
+    LBA_KCLASS_LINEARIZE_INIT,   /* cost and damping scale at the start of a round */
+    LBA_KCLASS_REDUCE,           /* fixed-order sum of the per-tile partial systems */
+    LBA_KCLASS_CHOLESKY,         /* FP64 factorisation and solve of the reduced system */
+    LBA_KCLASS_UPDATE,           /* back-substitution, retraction and trial cost */
+    LBA_KCLASS_DECIDE,           /* gain ratio, accept / reject, damping update */
+    LBA_KCLASS_INIT_REDUCE,
+    LBA_KCLASS_SETUP,
+    LBA_KCLASS_VALIDATE,
+    LBA_KCLASS_FLAGS,            /* chi-square outlier pass */
+    LBA_KCLASS_FINALIZE,
+    LBA_KCLASS_COUNT
+} lba_kernel_class;
+
+lba_status lba_profile_enable(lba_ctx *ctx, int32_t enable);
+lba_status lba_profile_read(const lba_ctx *ctx, int32_t kernel_class, int64_t *launches, double *total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBA_H */

@@ -1,0 +1,650 @@
+// C ABI of liblba.so: argument validation, launch planning, workspace layout and the
+// host-side sequencing of the Levenberg-Marquardt rounds.  All numerical work runs in
+// the kernels of the other translation units; this file only decides what to launch.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "lba.h"
+#include "lba_internal.h"
+
+using namespace lba;
+
+struct lba_ctx {
+    lba_options opt;
+    int device = 0;
+    int max_lds = 65536;
+    std::string err;
+    void *pinned = nullptr;
+    size_t pinned_bytes = 0;
+    // kernel timing
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<int> pending_cls;    // class of each recorded pair, pair i = events 2i, 2i+1
+    double prof_ms[LBA_KCLASS_COUNT] = {};
+    int64_t prof_n[LBA_KCLASS_COUNT] = {};
+};
+
+namespace {
+
+lba_status set_error(lba_ctx *ctx, lba_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    return st;
+}
+
+#define HIPCHK(call)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return set_error(ctx, LBA_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Plan {
+    int nw = 0;
+    bool mixed = false;
+    int waves = 4;
+    std::vector<WinInfo> win;
+    std::vector<Tile> tiles;
+    std::vector<int32_t> opt_map;
+    std::vector<int32_t> kf_off, pt_off, obs_off;
+    size_t lin_lds = 0, upd_lds = 0, chol_lds = 0;
+    int max_E2n = 0;
+    int64_t part_elems = 0;
+    int64_t red_elems = 0;
+    int64_t dp_elems = 0;
+    // workspace byte offsets
+    size_t o_win, o_tiles, o_opt, o_kfoff, o_ptoff, o_obsoff, o_upload_end;
+    size_t o_ptstart, o_ctl, o_T, o_X0, o_X1, o_part, o_partd, o_partu, o_red, o_redflag, o_dp,
+        o_stats, o_err, total;
+};
+
+int choose_points_per_tile(const lba_options &opt, int64_t total_points) {
+    if (opt.points_per_tile > 0) return opt.points_per_tile;
+    // about four blocks per compute unit over the whole batch, each block large enough
+    // that its partial reduced system is small next to the observations it reads
+    const int64_t target_blocks = 1024;
+    int64_t p = (total_points + target_blocks - 1) / target_blocks;
+    p = (p + 31) / 32 * 32;
+    p = std::max<int64_t>(64, std::min<int64_t>(4096, p));
+    return (int)p;
+}
+
+lba_status build_plan(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, Plan &pl) {
+    if (!P) return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "problem is NULL");
+    if (P->n_kf < 0 || P->n_pt < 0 || P->n_obs < 0)
+        return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "negative size");
+    if (P->n_levels < 1 || P->n_levels > kMaxLevels)
+        return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "n_levels must be in [1, %d]", kMaxLevels);
+    if (!P->sigma2) return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "sigma2 (host) is NULL");
+    for (int i = 0; i < P->n_levels; ++i)
+        if (!(P->sigma2[i] > 0.0) || !std::isfinite(P->sigma2[i]))
+            return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "sigma2[%d] must be positive", i);
+    if (P->n_kf > 0 && (!P->T_cw || !P->fixed))
+        return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "T_cw / fixed is NULL");
+    if (P->n_pt > 0 && !P->X_w) return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "X_w is NULL");
+    if (P->n_obs > 0 && (!P->obs_kf || !P->obs_pt || !P->obs_z || !P->obs_type || !P->obs_oct))
+        return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "an observation array is NULL");
+    if (!(P->cam.fx > 0.0) || !(P->cam.fy > 0.0) || !std::isfinite(P->cam.cx) ||
+        !std::isfinite(P->cam.cy) || !std::isfinite(P->cam.bf))
+        return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "invalid intrinsics");
+    const lba_options &opt = ctx->opt;
+    pl.mixed = opt.precision == LBA_PREC_MIXED;
+
+    if (B) {
+        if (B->n_windows < 1 || !B->kf_off || !B->pt_off || !B->obs_off)
+            return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "invalid batch description");
+        pl.nw = B->n_windows;
+        pl.kf_off.assign(B->kf_off, B->kf_off + pl.nw + 1);
+        pl.pt_off.assign(B->pt_off, B->pt_off + pl.nw + 1);
+        pl.obs_off.assign(B->obs_off, B->obs_off + pl.nw + 1);
+    } else {
+        pl.nw = 1;
+        pl.kf_off = {0, P->n_kf};
+        pl.pt_off = {0, P->n_pt};
+        pl.obs_off = {0, P->n_obs};
+    }
+    const int nw = pl.nw;
+    if (pl.kf_off[0] != 0 || pl.pt_off[0] != 0 || pl.obs_off[0] != 0 || pl.kf_off[nw] != P->n_kf ||
+        pl.pt_off[nw] != P->n_pt || pl.obs_off[nw] != P->n_obs)
+        return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "batch offsets must start at 0 and end at the totals");
+
+    int64_t total_points = P->n_pt;
+    const int ppt = choose_points_per_tile(opt, total_points);
+    const int kopt_max = pl.mixed ? kMaxKoptMixed : kMaxKoptFP64;
+    pl.win.resize(nw);
+    pl.opt_map.assign(P->n_kf, -1);
+    pl.tiles.clear();
+    int64_t part = 0, red = 0, dpo = 0;
+    int maxK = 1, maxn = 0;
+    for (int w = 0; w < nw; ++w) {
+        WinInfo &W = pl.win[w];
+        W.kf0 = pl.kf_off[w];
+        W.K = pl.kf_off[w + 1] - pl.kf_off[w];
+        W.pt0 = pl.pt_off[w];
+        W.M = pl.pt_off[w + 1] - pl.pt_off[w];
+        W.ob0 = pl.obs_off[w];
+        W.N = pl.obs_off[w + 1] - pl.obs_off[w];
+        if (W.K < 0 || W.M < 0 || W.N < 0)
+            return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "batch offsets decrease at window %d", w);
+        if (W.K > kMaxKf)
+            return set_error(ctx, LBA_ERR_UNSUPPORTED, "window %d has %d keyframes (limit %d)", w, W.K, kMaxKf);
+        int kopt = 0;
+        for (int k = 0; k < W.K; ++k) {
+            const uint8_t f = P->fixed[W.kf0 + k];
+            if (f > 1) return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "fixed[%d] is not 0/1", W.kf0 + k);
+            pl.opt_map[W.kf0 + k] = f ? -1 : kopt++;
+        }
+        if (kopt > kopt_max)
+            return set_error(ctx, LBA_ERR_UNSUPPORTED, "window %d has %d optimisable keyframes (limit %d for this precision)",
+                             w, kopt, kopt_max);
+        W.Kopt = kopt;
+        W.n = 6 * kopt;
+        W.E = W.n * (W.n + 1) / 2;
+        W.tile0 = (int)pl.tiles.size();
+        W.ntiles = (W.M + ppt - 1) / ppt;
+        for (int t = 0; t < W.ntiles; ++t) {
+            Tile T;
+            T.win = w;
+            T.p0 = W.pt0 + t * ppt;
+            T.p1 = W.pt0 + std::min(W.M, (t + 1) * ppt);
+            T.pad = 0;
+            pl.tiles.push_back(T);
+        }
+        W.part_stride = W.E + 2 * W.n;
+        W.part_off = part;
+        part += W.part_stride * W.ntiles;
+        W.red_off = (int32_t)red;
+        red += W.E + 2 * W.n;
+        W.dp_off = (int32_t)dpo;
+        dpo += W.n;
+        W.pad = 0;
+        maxK = std::max(maxK, W.K);
+        maxn = std::max(maxn, W.n);
+        pl.max_E2n = std::max(pl.max_E2n, W.E + 2 * W.n);
+    }
+    if (red > INT32_MAX) return set_error(ctx, LBA_ERR_UNSUPPORTED, "batch too large");
+    pl.part_elems = std::max<int64_t>(part, 1);
+    pl.red_elems = std::max<int64_t>(red, 1);
+    pl.dp_elems = std::max<int64_t>(dpo, 1);
+
+    // LDS: four wavefronts per block if the reduced system fits, fewer otherwise
+    pl.waves = 0;
+    for (int wv = 4; wv >= 1; wv /= 2) {
+        if (lin_lds_bytes(maxK, maxn, wv, pl.mixed) <= (size_t)ctx->max_lds &&
+            upd_lds_bytes(maxK, maxn, wv, pl.mixed) <= (size_t)ctx->max_lds) {
+            pl.waves = wv;
+            break;
+        }
+    }
+    if (!pl.waves)
+        return set_error(ctx, LBA_ERR_UNSUPPORTED, "reduced system of %d unknowns does not fit in LDS", maxn);
+    pl.lin_lds = lin_lds_bytes(maxK, maxn, pl.waves, pl.mixed);
+    pl.upd_lds = upd_lds_bytes(maxK, maxn, pl.waves, pl.mixed);
+    pl.chol_lds = chol_lds_bytes(maxn);
+    if (pl.chol_lds > (size_t)ctx->max_lds)
+        return set_error(ctx, LBA_ERR_UNSUPPORTED, "reduced system of %d unknowns does not fit in LDS", maxn);
+
+    // workspace layout (plan records first: they are uploaded in one copy)
+    size_t o = 0;
+    pl.o_win = o;    o = align256(o + sizeof(WinInfo) * nw);
+    pl.o_tiles = o;  o = align256(o + sizeof(Tile) * std::max<size_t>(pl.tiles.size(), 1));
+    pl.o_opt = o;    o = align256(o + sizeof(int32_t) * std::max(P->n_kf, 1));
+    pl.o_kfoff = o;  o = align256(o + sizeof(int32_t) * (nw + 1));
+    pl.o_ptoff = o;  o = align256(o + sizeof(int32_t) * (nw + 1));
+    pl.o_obsoff = o; o = align256(o + sizeof(int32_t) * (nw + 1));
+    pl.o_upload_end = o;
+    const size_t real = pl.mixed ? sizeof(float) : sizeof(double);
+    pl.o_ptstart = o; o = align256(o + sizeof(int32_t) * ((size_t)P->n_pt + 1));
+    pl.o_ctl = o;     o = align256(o + sizeof(Ctl) * nw);
+    pl.o_T = o;       o = align256(o + sizeof(double) * 12 * std::max(P->n_kf, 1));
+    pl.o_X0 = o;      o = align256(o + sizeof(double) * 3 * std::max(P->n_pt, 1));
+    pl.o_X1 = o;      o = align256(o + sizeof(double) * 3 * std::max(P->n_pt, 1));
+    pl.o_part = o;    o = align256(o + real * pl.part_elems);
+    pl.o_partd = o;   o = align256(o + sizeof(double) * 4 * std::max<size_t>(pl.tiles.size(), 1));
+    pl.o_partu = o;   o = align256(o + sizeof(double) * 4 * std::max<size_t>(pl.tiles.size(), 1));
+    pl.o_red = o;     o = align256(o + sizeof(double) * pl.red_elems);
+    pl.o_redflag = o; o = align256(o + sizeof(double) * nw);
+    pl.o_dp = o;      o = align256(o + sizeof(double) * pl.dp_elems);
+    pl.o_stats = o;   o = align256(o + sizeof(double) * LBA_STATS_LEN * nw);
+    pl.o_err = o;     o = align256(o + sizeof(int32_t) * 16);
+    pl.total = o;
+    return LBA_OK;
+}
+
+lba_status ensure_pinned(lba_ctx *ctx, size_t bytes) {
+    if (ctx->pinned_bytes >= bytes) return LBA_OK;
+    if (ctx->pinned) HIPCHK(hipHostFree(ctx->pinned));
+    ctx->pinned = nullptr;
+    ctx->pinned_bytes = 0;
+    size_t want = std::max<size_t>(bytes, 1 << 16);
+    HIPCHK(hipHostMalloc(&ctx->pinned, want, hipHostMallocDefault));
+    ctx->pinned_bytes = want;
+    return LBA_OK;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    bool changed = false;
+    hipError_t enter(int dev) {
+        hipError_t e = hipGetDevice(&prev);
+        if (e != hipSuccess) return e;
+        if (prev != dev) {
+            changed = true;
+            return hipSetDevice(dev);
+        }
+        return hipSuccess;
+    }
+    ~DeviceGuard() {
+        if (changed) (void)hipSetDevice(prev);
+    }
+};
+
+std::string describe_input_error(int32_t e) {
+    std::string s;
+    const char *names[] = {"observation keyframe index out of range", "observation point index out of range",
+                           "octave >= n_levels", "observation type not 0/1",
+                           "observations not grouped by point (obs_pt decreasing within a window)",
+                           "non-finite measurement", "non-finite pose", "non-finite point",
+                           "a point has more than 64 observations", "stereo observation with bf <= 0"};
+    for (int b = 0; b < 10; ++b)
+        if (e & (1 << b)) {
+            if (!s.empty()) s += "; ";
+            s += names[b];
+        }
+    return s;
+}
+
+// Launch `fn` (returning hipError_t) as kernel class `cls`, bracketed by events when
+// profiling is on.
+template <typename Fn>
+hipError_t timed(lba_ctx *ctx, int cls, hipStream_t s, Fn &&fn) {
+    if (!ctx->prof) return fn();
+    const size_t i = ctx->pending_cls.size();
+    while (ctx->ev_pool.size() < 2 * (i + 1)) {
+        hipEvent_t e;
+        hipError_t err = hipEventCreate(&e);
+        if (err != hipSuccess) return err;
+        ctx->ev_pool.push_back(e);
+    }
+    hipError_t e = hipEventRecord(ctx->ev_pool[2 * i], s);
+    if (e != hipSuccess) return e;
+    e = fn();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(ctx->ev_pool[2 * i + 1], s);
+    if (e != hipSuccess) return e;
+    ctx->pending_cls.push_back(cls);
+    return hipSuccess;
+}
+
+// fold the recorded event pairs into the counters (the stream has been synchronised)
+hipError_t collect_timing(lba_ctx *ctx) {
+    for (size_t i = 0; i < ctx->pending_cls.size(); ++i) {
+        float ms = 0.0f;
+        hipError_t e = hipEventElapsedTime(&ms, ctx->ev_pool[2 * i], ctx->ev_pool[2 * i + 1]);
+        if (e != hipSuccess) return e;
+        ctx->prof_ms[ctx->pending_cls[i]] += ms;
+        ctx->prof_n[ctx->pending_cls[i]] += 1;
+    }
+    ctx->pending_cls.clear();
+    return hipSuccess;
+}
+
+lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lba_result *R, void *ws,
+                      size_t ws_bytes, void *stream_ptr) {
+    if (!ctx) return LBA_ERR_INVALID_ARGUMENT;
+    ctx->err.clear();
+    if (!R) return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "result is NULL");
+    Plan pl;
+    lba_status st = build_plan(ctx, P, B, pl);
+    if (st != LBA_OK) return st;
+    if (P->n_kf > 0 && !R->T_out) return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "T_out is NULL");
+    if (P->n_pt > 0 && !R->X_out) return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "X_out is NULL");
+    if (P->n_obs > 0 && !R->outlier) return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "outlier is NULL");
+    if (!ws || ws_bytes < pl.total)
+        return set_error(ctx, LBA_ERR_WORKSPACE_TOO_SMALL, "workspace of %zu bytes given, %zu needed", ws_bytes,
+                         pl.total);
+    if (((uintptr_t)ws) & 255) return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "workspace not 256-byte aligned");
+    const lba_options &opt = ctx->opt;
+    if (opt.iters_round1 < 0 || opt.iters_round2 < 0 || opt.max_trials < 1)
+        return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "invalid iteration counts");
+
+    DeviceGuard dg;
+    HIPCHK(dg.enter(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream_ptr);
+    unsigned char *wsb = static_cast<unsigned char *>(ws);
+    const int nw = pl.nw;
+
+    // ---- upload the plan ------------------------------------------------------------
+    const size_t down_bytes = std::max(sizeof(Ctl) * nw, sizeof(double) * LBA_STATS_LEN * nw) + 256;
+    st = ensure_pinned(ctx, pl.o_upload_end + down_bytes);
+    if (st != LBA_OK) return st;
+    unsigned char *up = static_cast<unsigned char *>(ctx->pinned);
+    unsigned char *down = up + pl.o_upload_end;
+    memcpy(up + pl.o_win, pl.win.data(), sizeof(WinInfo) * nw);
+    if (!pl.tiles.empty()) memcpy(up + pl.o_tiles, pl.tiles.data(), sizeof(Tile) * pl.tiles.size());
+    if (P->n_kf > 0) memcpy(up + pl.o_opt, pl.opt_map.data(), sizeof(int32_t) * P->n_kf);
+    memcpy(up + pl.o_kfoff, pl.kf_off.data(), sizeof(int32_t) * (nw + 1));
+    memcpy(up + pl.o_ptoff, pl.pt_off.data(), sizeof(int32_t) * (nw + 1));
+    memcpy(up + pl.o_obsoff, pl.obs_off.data(), sizeof(int32_t) * (nw + 1));
+    HIPCHK(hipMemcpyAsync(wsb, up, pl.o_upload_end, hipMemcpyHostToDevice, s));
+
+    // ---- constants and argument packs ----------------------------------------------------
+    SolveConsts c;
+    memset(&c, 0, sizeof(c));
+    c.cam = {P->cam.fx, P->cam.fy, P->cam.cx, P->cam.cy, P->cam.bf};
+    c.huber2[0] = opt.huber2_mono;
+    c.huber2[1] = opt.huber2_stereo;
+    c.chi2[0] = opt.chi2_mono;
+    c.chi2[1] = opt.chi2_stereo;
+    c.tau = opt.tau;
+    for (int i = 0; i < P->n_levels; ++i) c.inv_sigma2[i] = 1.0 / P->sigma2[i];
+    c.iters[0] = opt.iters_round1;
+    c.iters[1] = opt.iters_round2;
+    c.max_trials = opt.max_trials;
+    c.n_windows = nw;
+
+    auto W_ = [&](size_t off) { return reinterpret_cast<void *>(wsb + off); };
+    const WinInfo *d_win = static_cast<const WinInfo *>(W_(pl.o_win));
+    const Tile *d_tiles = static_cast<const Tile *>(W_(pl.o_tiles));
+    const int32_t *d_opt = static_cast<const int32_t *>(W_(pl.o_opt));
+    int32_t *d_ptstart = static_cast<int32_t *>(W_(pl.o_ptstart));
+    Ctl *d_ctl = static_cast<Ctl *>(W_(pl.o_ctl));
+    double *d_T = static_cast<double *>(W_(pl.o_T));
+    double *d_X0 = static_cast<double *>(W_(pl.o_X0));
+    double *d_X1 = static_cast<double *>(W_(pl.o_X1));
+    double *d_partd = static_cast<double *>(W_(pl.o_partd));
+    double *d_partu = static_cast<double *>(W_(pl.o_partu));
+    double *d_red = static_cast<double *>(W_(pl.o_red));
+    double *d_redflag = static_cast<double *>(W_(pl.o_redflag));
+    double *d_dp = static_cast<double *>(W_(pl.o_dp));
+    double *d_stats = static_cast<double *>(W_(pl.o_stats));
+    int32_t *d_err = static_cast<int32_t *>(W_(pl.o_err));
+
+    ObsView ob;
+    ob.kf = P->obs_kf;
+    ob.pt = P->obs_pt;
+    ob.z = P->obs_z;
+    ob.type = P->obs_type;
+    ob.oct = P->obs_oct;
+    ob.n_obs = P->n_obs;
+    ob.z_f32 = P->obs_z_f32 ? 1 : 0;
+
+    MiscArgs m;
+    memset(&m, 0, sizeof(m));
+    m.win = d_win;
+    m.kf_off_dev = static_cast<const int32_t *>(W_(pl.o_kfoff));
+    m.pt_off_dev = static_cast<const int32_t *>(W_(pl.o_ptoff));
+    m.obs_off_dev = static_cast<const int32_t *>(W_(pl.o_obsoff));
+    m.T_in = P->T_cw;
+    m.X_in = P->X_w;
+    m.T = d_T;
+    m.X0 = d_X0;
+    m.X1 = d_X1;
+    m.ctl = d_ctl;
+    m.pt_start = d_ptstart;
+    m.obs = ob;
+    m.flags = R->outlier;
+    m.T_out = R->T_out;
+    m.X_out = R->X_out;
+    m.stats = d_stats;
+    m.err = d_err;
+    m.n_kf = P->n_kf;
+    m.n_pt = P->n_pt;
+    m.n_levels = P->n_levels;
+    m.c = c;
+
+    HIPCHK(timed(ctx, LBA_KCLASS_SETUP, s, [&] { return launch_setup(m, nw, s); }));
+    HIPCHK(timed(ctx, LBA_KCLASS_VALIDATE, s, [&] { return launch_validate(m, s); }));
+    HIPCHK(hipMemcpyAsync(down, d_err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    int32_t in_err;
+    memcpy(&in_err, down, sizeof(int32_t));
+    HIPCHK(collect_timing(ctx));
+    if (in_err) return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "invalid input: %s", describe_input_error(in_err).c_str());
+
+    const int ntiles = (int)pl.tiles.size();
+    LinArgs la;
+    memset(&la, 0, sizeof(la));
+    la.win = d_win;
+    la.tiles = d_tiles;
+    la.opt_map = d_opt;
+    la.pt_start = d_ptstart;
+    la.T = d_T;
+    la.X0 = d_X0;
+    la.X1 = d_X1;
+    la.ctl = d_ctl;
+    la.obs = ob;
+    la.part = W_(pl.o_part);
+    la.partd = d_partd;
+    la.waves = pl.waves;
+    la.c = c;
+
+    ReduceArgs ra;
+    ra.win = d_win;
+    ra.ctl = d_ctl;
+    ra.part = W_(pl.o_part);
+    ra.partd = d_partd;
+    ra.red = d_red;
+    ra.redflag = d_redflag;
+    ra.max_E2n = pl.max_E2n;
+    ra.mixed = pl.mixed;
+
+    CholArgs ca;
+    ca.win = d_win;
+    ca.ctl = d_ctl;
+    ca.red = d_red;
+    ca.redflag = d_redflag;
+    ca.dp = d_dp;
+
+    UpdArgs ua;
+    memset(&ua, 0, sizeof(ua));
+    ua.win = d_win;
+    ua.tiles = d_tiles;
+    ua.opt_map = d_opt;
+    ua.pt_start = d_ptstart;
+    ua.T = d_T;
+    ua.X0 = d_X0;
+    ua.X1 = d_X1;
+    ua.ctl = d_ctl;
+    ua.dp = d_dp;
+    ua.obs = ob;
+    ua.partu = d_partu;
+    ua.waves = pl.waves;
+    ua.c = c;
+
+    DecideArgs da;
+    da.win = d_win;
+    da.ctl = d_ctl;
+    da.opt_map = d_opt;
+    da.T = d_T;
+    da.dp = d_dp;
+    da.partu = d_partu;
+    da.c = c;
+
+    InitReduceArgs ia;
+    ia.win = d_win;
+    ia.ctl = d_ctl;
+    ia.part = W_(pl.o_part);
+    ia.partd = d_partd;
+    ia.mixed = pl.mixed;
+    ia.c = c;
+
+    std::vector<Ctl> hctl(nw);
+    for (int round = 1; round <= 2; ++round) {
+        const int iters = round == 1 ? opt.iters_round1 : opt.iters_round2;
+        const uint8_t *mask = nullptr;
+        if (round == 2) {
+            HIPCHK(timed(ctx, LBA_KCLASS_FLAGS, s, [&] { return launch_flags(m, s); }));
+            mask = R->outlier;
+        }
+        const int robust = round == 1 ? 1 : (opt.round2_robust ? 1 : 0);
+        la.mask = mask;
+        la.robust = robust;
+        ua.mask = mask;
+        ua.robust = robust;
+        da.round = round;
+        ia.round = round;
+        HIPCHK(timed(ctx, LBA_KCLASS_LINEARIZE_INIT, s,
+                     [&] { return launch_linearize(la, ntiles, pl.lin_lds, true, pl.mixed, s); }));
+        HIPCHK(timed(ctx, LBA_KCLASS_INIT_REDUCE, s, [&] { return launch_init_reduce(ia, nw, s); }));
+        int steps_done = 0;
+        int nsteps = iters;
+        const int max_steps = iters * opt.max_trials;
+        while (nsteps > 0 && steps_done < max_steps) {
+            for (int k = 0; k < nsteps; ++k) {
+                HIPCHK(timed(ctx, LBA_KCLASS_LINEARIZE, s,
+                             [&] { return launch_linearize(la, ntiles, pl.lin_lds, false, pl.mixed, s); }));
+                HIPCHK(timed(ctx, LBA_KCLASS_REDUCE, s, [&] { return launch_reduce(ra, nw, s); }));
+                HIPCHK(timed(ctx, LBA_KCLASS_CHOLESKY, s, [&] { return launch_cholesky(ca, nw, pl.chol_lds, s); }));
+                HIPCHK(timed(ctx, LBA_KCLASS_UPDATE, s,
+                             [&] { return launch_update(ua, ntiles, pl.upd_lds, pl.mixed, s); }));
+                HIPCHK(timed(ctx, LBA_KCLASS_DECIDE, s, [&] { return launch_decide(da, nw, s); }));
+            }
+            steps_done += nsteps;
+            HIPCHK(hipMemcpyAsync(down, d_ctl, sizeof(Ctl) * nw, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            memcpy(hctl.data(), down, sizeof(Ctl) * nw);
+            int need = 0;
+            for (int w = 0; w < nw; ++w)
+                if (hctl[w].running) need = std::max(need, std::max(1, iters - hctl[w].iter));
+            nsteps = std::min(need, max_steps - steps_done);
+        }
+    }
+    HIPCHK(timed(ctx, LBA_KCLASS_FLAGS, s, [&] { return launch_flags(m, s); }));
+    HIPCHK(timed(ctx, LBA_KCLASS_FINALIZE, s, [&] { return launch_finalize(m, nw, s); }));
+    if (R->stats) {
+        HIPCHK(hipMemcpyAsync(down, d_stats, sizeof(double) * LBA_STATS_LEN * nw, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        memcpy(R->stats, down, sizeof(double) * LBA_STATS_LEN * nw);
+    } else {
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    HIPCHK(collect_timing(ctx));
+    return LBA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t lba_abi_version(void) { return LBA_ABI_VERSION; }
+
+const char *lba_status_string(lba_status status) {
+    switch (status) {
+        case LBA_OK: return "ok";
+        case LBA_ERR_INVALID_ARGUMENT: return "invalid argument";
+        case LBA_ERR_OUT_OF_MEMORY: return "out of memory";
+        case LBA_ERR_HIP: return "HIP runtime error";
+        case LBA_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+        case LBA_ERR_UNSUPPORTED: return "unsupported problem size";
+    }
+    return "unknown status";
+}
+
+void lba_default_options(lba_options *o) {
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->precision = LBA_PREC_FP64;
+    o->iters_round1 = 5;
+    o->iters_round2 = 10;
+    o->max_trials = 10;
+    o->round2_robust = 1;
+    o->check_inputs = 1;
+    o->huber2_mono = 5.991;
+    o->huber2_stereo = 7.815;
+    o->chi2_mono = 5.991;
+    o->chi2_stereo = 7.815;
+    o->tau = 1e-5;
+    o->points_per_tile = 0;
+}
+
+lba_status lba_create(const lba_options *opt, int32_t device, lba_ctx **out) {
+    if (!out) return LBA_ERR_INVALID_ARGUMENT;
+    *out = nullptr;
+    lba_ctx *ctx = new (std::nothrow) lba_ctx();
+    if (!ctx) return LBA_ERR_OUT_OF_MEMORY;
+    if (opt) ctx->opt = *opt;
+    else lba_default_options(&ctx->opt);
+    ctx->device = device;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) {
+        delete ctx;
+        return LBA_ERR_INVALID_ARGUMENT;
+    }
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
+        ctx->max_lds = lds;
+    *out = ctx;
+    return LBA_OK;
+}
+
+void lba_destroy(lba_ctx *ctx) {
+    if (!ctx) return;
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+lba_status lba_profile_enable(lba_ctx *ctx, int32_t enable) {
+    if (!ctx) return LBA_ERR_INVALID_ARGUMENT;
+    ctx->prof = enable != 0;
+    ctx->pending_cls.clear();
+    for (int i = 0; i < LBA_KCLASS_COUNT; ++i) {
+        ctx->prof_ms[i] = 0.0;
+        ctx->prof_n[i] = 0;
+    }
+    return LBA_OK;
+}
+
+lba_status lba_profile_read(const lba_ctx *ctx, int32_t kernel_class, int64_t *launches, double *total_ms) {
+    if (!ctx || kernel_class < 0 || kernel_class >= LBA_KCLASS_COUNT) return LBA_ERR_INVALID_ARGUMENT;
+    if (launches) *launches = ctx->prof_n[kernel_class];
+    if (total_ms) *total_ms = ctx->prof_ms[kernel_class];
+    return LBA_OK;
+}
+
+const char *lba_last_error(const lba_ctx *ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
+
+lba_status lba_set_options(lba_ctx *ctx, const lba_options *opt) {
+    if (!ctx || !opt) return LBA_ERR_INVALID_ARGUMENT;
+    ctx->opt = *opt;
+    return LBA_OK;
+}
+
+lba_status lba_workspace_size(lba_ctx *ctx, const lba_problem *problem, const lba_batch *batch, size_t *bytes) {
+    if (!ctx || !bytes) return LBA_ERR_INVALID_ARGUMENT;
+    ctx->err.clear();
+    Plan pl;
+    lba_status st = build_plan(ctx, problem, batch, pl);
+    if (st != LBA_OK) return st;
+    *bytes = pl.total;
+    return LBA_OK;
+}
+
+lba_status lba_solve(lba_ctx *ctx, const lba_problem *problem, lba_result *result, void *workspace,
+                     size_t workspace_bytes, void *stream) {
+    return solve_impl(ctx, problem, nullptr, result, workspace, workspace_bytes, stream);
+}
+
+lba_status lba_solve_batch(lba_ctx *ctx, const lba_problem *problem, const lba_batch *batch, lba_result *result,
+                           void *workspace, size_t workspace_bytes, void *stream) {
+    if (!batch) {
+        if (ctx) ctx->err = "batch is NULL";
+        return LBA_ERR_INVALID_ARGUMENT;
+    }
+    return solve_impl(ctx, problem, batch, result, workspace, workspace_bytes, stream);
+}
+
+}  // extern "C"
