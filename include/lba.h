@@ -158,8 +158,8 @@ lba_status lba_set_options(lba_ctx *ctx, const lba_options *opt);
 
 /* Bytes of DEVICE workspace lba_solve / lba_solve_batch need for this problem
  * (batch NULL: one window).  Limits: per window n_kf <= 128, optimisable keyframes
- * <= 30 (FP64) or <= 40 (mixed), at most 64 observations per point; beyond them the
- * call returns LBA_ERR_UNSUPPORTED. */
+ * <= 30 (the FP64 reduced system of 180 unknowns is factorised in LDS), at most 64
+ * observations per point; beyond them the call returns LBA_ERR_UNSUPPORTED. */
 lba_status lba_workspace_size(lba_ctx *ctx, const lba_problem *problem, const lba_batch *batch,
                               size_t *bytes);
 

@@ -125,17 +125,21 @@ hipError_t launch_flags(const MiscArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-// copy-out of the final state and per-window statistics (one block per window)
+// copy-out of the final state and per-window statistics: grid (x, window); every block
+// copies a slice of its window's points, block x == 0 also the poses and the statistics
 __global__ __launch_bounds__(256) void k_finalize(MiscArgs a) {
     __shared__ int cnt[4];
-    const int w = blockIdx.x;
+    const int w = blockIdx.y;
     const WinInfo W = a.win[w];
     const Ctl c = a.ctl[w];
     const double *X = c.cur ? a.X1 : a.X0;
+    const int64_t x0 = 3 * (int64_t)W.pt0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * (int64_t)W.M;
+         i += (int64_t)gridDim.x * blockDim.x)
+        a.X_out[x0 + i] = X[x0 + i];
+    if (blockIdx.x != 0) return;
     for (int i = threadIdx.x; i < 12 * W.K; i += blockDim.x)
         a.T_out[12 * (int64_t)W.kf0 + i] = a.T[12 * (int64_t)W.kf0 + i];
-    for (int i = threadIdx.x; i < 3 * W.M; i += blockDim.x)
-        a.X_out[3 * (int64_t)W.pt0 + i] = X[3 * (int64_t)W.pt0 + i];
     int n = 0;
     for (int i = threadIdx.x; i < W.N; i += blockDim.x) n += a.flags[(int64_t)W.ob0 + i];
 #pragma unroll
@@ -162,7 +166,9 @@ __global__ __launch_bounds__(256) void k_finalize(MiscArgs a) {
 
 hipError_t launch_finalize(const MiscArgs &a, int n_windows, hipStream_t s) {
     if (n_windows <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_finalize, dim3(n_windows), dim3(256), 0, s, a);
+    int bx = (int)((3 * (int64_t)a.n_pt / n_windows + 1023) / 1024);
+    bx = bx < 1 ? 1 : (bx > 256 ? 256 : bx);
+    hipLaunchKernelGGL(k_finalize, dim3(bx, n_windows), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

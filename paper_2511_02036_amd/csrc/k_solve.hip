@@ -6,44 +6,69 @@
 namespace lba {
 
 // ------------------------------------------------------------------------------------
-// partial sums -> reduced system.  grid = (ceil(max(E + 2n) / 256), n_windows); each
-// thread sums one entry over the window's tiles in tile order (deterministic).
+// partial sums -> reduced system.  Each block owns 64 entries of one window; its four
+// wavefronts sum the tiles t = g, g + 4, ... (g = wavefront) and the four partial sums
+// are combined in a fixed order, so the result does not depend on scheduling.
 // ------------------------------------------------------------------------------------
 template <typename Real>
 __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a) {
+    __shared__ double acc4[4][64];
     const int w = blockIdx.y;
     const WinInfo W = a.win[w];
     if (!a.ctl[w].running) return;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int i = blockIdx.x * 64 + lane;
     const int tot = W.E + 2 * W.n;
-    const Real *part = static_cast<const Real *>(a.part) + W.part_off;
-    if (i < tot) {
-        double acc = 0.0;
-        for (int t = 0; t < W.ntiles; ++t) acc += (double)part[(int64_t)t * W.part_stride + i];
-        a.red[W.red_off + i] = acc;
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (blockIdx.x == 0 && g == 0) {
+        // the window's point-block failure flag (written even when the system is empty)
         double fl = 0.0;
-        for (int t = 0; t < W.ntiles; ++t) fl = fmax(fl, a.partd[4 * (W.tile0 + t) + 2]);
-        a.redflag[w] = fl;
+        for (int t = lane; t < W.ntiles; t += 64) fl = fmax(fl, a.partd[4 * (W.tile0 + t) + 2]);
+        fl = wave_max(fl);
+        if (lane == 0) a.redflag[w] = fl;
     }
+    if (blockIdx.x * 64 >= tot) return;
+    const Real *part = static_cast<const Real *>(a.part) + W.part_off;
+    double s0 = 0.0, s1 = 0.0;
+    if (i < tot) {
+        int t = g;
+        for (; t + 4 < W.ntiles; t += 8) {
+            s0 += (double)part[(int64_t)t * W.part_stride + i];
+            s1 += (double)part[(int64_t)(t + 4) * W.part_stride + i];
+        }
+        for (; t < W.ntiles; t += 4) s0 += (double)part[(int64_t)t * W.part_stride + i];
+    }
+    acc4[g][lane] = s0 + s1;
+    __syncthreads();
+    if (g == 0 && i < tot) a.red[W.red_off + i] = (acc4[0][lane] + acc4[1][lane]) + (acc4[2][lane] + acc4[3][lane]);
 }
 
 hipError_t launch_reduce(const ReduceArgs &a, int n_windows, hipStream_t s) {
     if (n_windows <= 0) return hipSuccess;
-    dim3 grid((a.max_E2n + 255) / 256 > 0 ? (a.max_E2n + 255) / 256 : 1, n_windows), block(256);
+    dim3 grid((a.max_E2n + 63) / 64 > 0 ? (a.max_E2n + 63) / 64 : 1, n_windows), block(256);
     if (a.mixed) hipLaunchKernelGGL(k_reduce<float>, grid, block, 0, s, a);
     else hipLaunchKernelGGL(k_reduce<double>, grid, block, 0, s, a);
     return hipGetLastError();
 }
 
 // ------------------------------------------------------------------------------------
-// dense FP64 Cholesky of S + lambda I (packed lower triangle in LDS) and the two
-// triangular solves, one wavefront per window (wave-synchronous, no block barriers)
+// Dense FP64 Cholesky of S + lambda I and the two triangular solves, one block of 512
+// threads per window, S held as a packed lower triangle in LDS.  Right-looking with
+// 8-column panels.  Per panel every thread reads the 8x8 diagonal block (broadcast LDS
+// reads) and factors it redundantly in registers, so no lane-to-lane traffic sits on the
+// serial path; each thread then solves one row of the panel below the block, and after
+// one barrier all threads apply the rank-8 update to the trailing triangle in 4x4
+// register tiles.  The solves reuse the panels: the 8x8 triangular solve is again done
+// redundantly by every thread, followed by a parallel update of the other rows.
 // ------------------------------------------------------------------------------------
+#ifndef LBA_CHOL_NB
+#define LBA_CHOL_NB 8
+#endif
+constexpr int kNB = LBA_CHOL_NB;
+constexpr int kCholThreads = 512;
+
 size_t chol_lds_bytes(int n) {
     const size_t E = (size_t)n * (n + 1) / 2;
-    return sizeof(double) * (E + 2 * (size_t)n + 2);
+    return sizeof(double) * (E + 3 * (size_t)n + (size_t)kNB * n) + 64;
 }
 
 __device__ __forceinline__ void tri_decode(int e, int &ii, int &jj) {
@@ -54,84 +79,237 @@ __device__ __forceinline__ void tri_decode(int e, int &ii, int &jj) {
     jj = e - r * (r + 1) / 2;
 }
 
-__global__ __launch_bounds__(64) void k_cholesky(CholArgs a) {
+// factor the nbk x nbk diagonal block whose top-left entry is (c0, c0) into registers:
+// L (lower, row-major kNB x kNB) and its reciprocal diagonal; returns false on a
+// non-positive or non-finite pivot
+__device__ __forceinline__ bool diag_block_factor(const double *A, int c0, int nbk, double (&L)[kNB][kNB],
+                                                  double (&rd)[kNB]) {
+    bool ok = true;
+#pragma unroll
+    for (int i = 0; i < kNB; ++i)
+#pragma unroll
+        for (int j = 0; j < kNB; ++j) L[i][j] = (i < nbk && j <= i) ? A[packed_lower(c0 + i, c0 + j)] : 0.0;
+#pragma unroll
+    for (int j = 0; j < kNB; ++j) {
+        if (j < nbk) {
+            double d = L[j][j];
+#pragma unroll
+            for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
+            if (!(d > 0.0) || !isfinite(d)) ok = false;
+            const double l = sqrt(d);
+            const double r = 1.0 / l;
+            L[j][j] = l;
+            rd[j] = r;
+#pragma unroll
+            for (int i = j + 1; i < kNB; ++i) {
+                double v = L[i][j];
+#pragma unroll
+                for (int k = 0; k < j; ++k) v -= L[i][k] * L[j][k];
+                L[i][j] = v * r;
+            }
+        } else {
+            rd[j] = 0.0;
+        }
+    }
+    return ok;
+}
+
+__global__ __launch_bounds__(kCholThreads) void k_cholesky(CholArgs a) {
     extern __shared__ __align__(16) double cs[];
+    __shared__ int s_fail;
     const int w = blockIdx.x;
     const WinInfo W = a.win[w];
     Ctl *ctl = a.ctl + w;
     if (!ctl->running) return;
     const int n = W.n, E = W.E;
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int nth = blockDim.x;
     const double lambda = ctl->lambda;
-    double *A = cs;          // E
+    double *A = cs;          // E, packed lower
     double *y = cs + E;      // n
     double *bp = y + n;      // n
+    double *rdiag = bp + n;  // n reciprocal pivots
+    double *Ld = rdiag + n;  // n x kNB: factored diagonal blocks (row r holds L[r][c0 .. r])
     const double *red = a.red + W.red_off;
-    for (int i = lane; i < E; i += 64) A[i] = red[i];
-    for (int i = lane; i < n; i += 64) {
+    for (int i = tid; i < E; i += nth) A[i] = red[i];
+    for (int i = tid; i < n; i += nth) {
         y[i] = red[E + i];
         bp[i] = red[E + n + i];
     }
-    wave_sync();
-    for (int i = lane; i < n; i += 64) A[packed_lower(i, i)] += lambda;
-    wave_sync();
-    int ok = a.redflag[w] == 0.0;
-    for (int k = 0; k < n && ok; ++k) {
-        const double d = A[packed_lower(k, k)];
-        if (!(d > 0.0) || !isfinite(d)) {
-            ok = 0;
-            break;
+    if (tid == 0) s_fail = a.redflag[w] != 0.0;
+    __syncthreads();
+    for (int i = tid; i < n; i += nth) A[packed_lower(i, i)] += lambda;
+    __syncthreads();
+
+    // ---- factorisation ----------------------------------------------------------------
+    for (int c0 = 0; c0 < n; c0 += kNB) {
+        const int nbk = min(kNB, n - c0);
+        const int b0 = c0 + nbk;
+        double L[kNB][kNB], rd[kNB];
+        const bool ok = diag_block_factor(A, c0, nbk, L, rd);
+        if (!ok) {
+            if (tid == 0) s_fail = 1;
+        } else {
+            // panel rows below the diagonal block: L[r][c0+j] = (A[r][c0+j] - sum_k L[r][c0+k] L[c0+j][c0+k]) / L[c0+j][c0+j]
+            for (int r = b0 + tid; r < n; r += nth) {
+                double x[kNB];
+#pragma unroll
+                for (int j = 0; j < kNB; ++j) x[j] = j < nbk ? A[packed_lower(r, c0 + j)] : 0.0;
+#pragma unroll
+                for (int j = 0; j < kNB; ++j) {
+                    double v = x[j];
+#pragma unroll
+                    for (int k = 0; k < j; ++k) v -= x[k] * L[j][k];
+                    x[j] = v * rd[j];
+                }
+#pragma unroll
+                for (int j = 0; j < kNB; ++j)
+                    if (j < nbk) A[packed_lower(r, c0 + j)] = x[j];
+            }
+            // the factored diagonal block goes to Ld (A's copy is still being read by
+            // other threads in this phase)
+            if (tid < nbk * kNB) {
+                const int i = tid / kNB, j = tid % kNB;
+                double v = 0.0;
+#pragma unroll
+                for (int ii = 0; ii < kNB; ++ii)
+#pragma unroll
+                    for (int jj = 0; jj < kNB; ++jj)
+                        if (ii == i && jj == j) v = L[ii][jj];
+                Ld[(c0 + i) * kNB + j] = v;
+            }
+            if (tid < nbk) {
+                double v = 0.0;
+#pragma unroll
+                for (int jj = 0; jj < kNB; ++jj)
+                    if (jj == tid) v = rd[jj];
+                rdiag[c0 + tid] = v;
+            }
         }
-        const double ld = sqrt(d), il = 1.0 / ld;
-        wave_sync();
-        for (int i = k + 1 + lane; i < n; i += 64) A[packed_lower(i, k)] *= il;
-        if (lane == 0) A[packed_lower(k, k)] = ld;
-        wave_sync();
-        const int m = n - k - 1;
-        const int tot = m * (m + 1) / 2;
-        for (int e = lane; e < tot; e += 64) {
-            int ii, jj;
-            tri_decode(e, ii, jj);
-            const int i = k + 1 + ii, j = k + 1 + jj;
-            A[packed_lower(i, j)] -= A[packed_lower(i, k)] * A[packed_lower(j, k)];
+        __syncthreads();
+        if (s_fail) break;
+        // trailing update A[i][j] -= sum_kk L[i][c0+kk] L[j][c0+kk], b0 <= j <= i < n
+        const int m = n - b0;
+        const int T4 = (m + 3) / 4;
+        const int ntile = T4 * (T4 + 1) / 2;
+        for (int t = tid; t < ntile; t += nth) {
+            int I, J;
+            tri_decode(t, I, J);
+            const int i0 = b0 + 4 * I, j0 = b0 + 4 * J;
+            double ai[4][kNB], aj[4][kNB];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int ri = i0 + u, rj = j0 + u;
+#pragma unroll
+                for (int kk = 0; kk < kNB; ++kk) {
+                    ai[u][kk] = (ri < n && kk < nbk) ? A[packed_lower(ri, c0 + kk)] : 0.0;
+                    aj[u][kk] = (rj < n && kk < nbk) ? A[packed_lower(rj, c0 + kk)] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = i0 + u, j = j0 + v;
+                    if (i < n && j <= i) {
+                        double acc = 0.0;
+#pragma unroll
+                        for (int kk = 0; kk < kNB; ++kk) acc += ai[u][kk] * aj[v][kk];
+                        A[packed_lower(i, j)] -= acc;
+                    }
+                }
+            }
         }
-        wave_sync();
+        __syncthreads();
+    }
+    const int ok = !s_fail;
+
+    // ---- L y = r, then L^T x = y (one barrier per panel) --------------------------------
+    if (ok) {
+        for (int c0 = 0; c0 < n; c0 += kNB) {
+            const int nbk = min(kNB, n - c0);
+            double yp[kNB];
+#pragma unroll
+            for (int j = 0; j < kNB; ++j) {
+                if (j < nbk) {
+                    double v = y[c0 + j];
+#pragma unroll
+                    for (int k = 0; k < j; ++k) v -= Ld[(c0 + j) * kNB + k] * yp[k];
+                    yp[j] = v * rdiag[c0 + j];
+                } else {
+                    yp[j] = 0.0;
+                }
+            }
+            __syncthreads();   // every thread has read y[c0 .. c0 + nbk)
+            if (tid < nbk) {
+                double v = 0.0;
+#pragma unroll
+                for (int j = 0; j < kNB; ++j)
+                    if (j == tid) v = yp[j];
+                y[c0 + tid] = v;
+            }
+            for (int i = c0 + nbk + tid; i < n; i += nth) {
+                double acc = 0.0;
+#pragma unroll
+                for (int kk = 0; kk < kNB; ++kk)
+                    if (kk < nbk) acc += A[packed_lower(i, c0 + kk)] * yp[kk];
+                y[i] -= acc;
+            }
+            __syncthreads();
+        }
+        const int last = n > 0 ? ((n - 1) / kNB) * kNB : 0;
+        for (int c0 = last; c0 >= 0 && n > 0; c0 -= kNB) {
+            const int nbk = min(kNB, n - c0);
+            double xp[kNB];
+#pragma unroll
+            for (int j = kNB - 1; j >= 0; --j) {
+                if (j < nbk) {
+                    double v = y[c0 + j];
+#pragma unroll
+                    for (int k = j + 1; k < kNB; ++k)
+                        if (k < nbk) v -= Ld[(c0 + k) * kNB + j] * xp[k];
+                    xp[j] = v * rdiag[c0 + j];
+                } else {
+                    xp[j] = 0.0;
+                }
+            }
+            __syncthreads();
+            if (tid < nbk) {
+                double v = 0.0;
+#pragma unroll
+                for (int j = 0; j < kNB; ++j)
+                    if (j == tid) v = xp[j];
+                y[c0 + tid] = v;
+            }
+            for (int j = tid; j < c0; j += nth) {
+                double acc = 0.0;
+#pragma unroll
+                for (int kk = 0; kk < kNB; ++kk)
+                    if (kk < nbk) acc += A[packed_lower(c0 + kk, j)] * xp[kk];
+                y[j] -= acc;
+            }
+            __syncthreads();
+        }
     }
     double *dp = a.dp + W.dp_off;
-    if (ok) {
-        // L y = r
-        for (int k = 0; k < n; ++k) {
-            const double yk = y[k] / A[packed_lower(k, k)];
-            wave_sync();
-            for (int i = k + 1 + lane; i < n; i += 64) y[i] -= A[packed_lower(i, k)] * yk;
-            if (lane == 0) y[k] = yk;
-            wave_sync();
+    if (tid < 64) {
+        double den = 0.0;
+        for (int i = lane; i < n; i += 64) {
+            const double x = ok ? y[i] : 0.0;
+            dp[i] = x;
+            den += x * (lambda * x + bp[i]);
         }
-        // L^T x = y
-        for (int k = n - 1; k >= 0; --k) {
-            const double xk = y[k] / A[packed_lower(k, k)];
-            wave_sync();
-            for (int i = lane; i < k; i += 64) y[i] -= A[packed_lower(k, i)] * xk;
-            if (lane == 0) y[k] = xk;
-            wave_sync();
+        den = wave_sum(den);
+        if (lane == 0) {
+            ctl->solve_ok = ok;
+            ctl->denom_p = den;
         }
-    }
-    double den = 0.0;
-    for (int i = lane; i < n; i += 64) {
-        const double x = ok ? y[i] : 0.0;
-        dp[i] = x;
-        den += x * (lambda * x + bp[i]);
-    }
-    den = wave_sum(den);
-    if (lane == 0) {
-        ctl->solve_ok = ok;
-        ctl->denom_p = den;
     }
 }
 
 hipError_t launch_cholesky(const CholArgs &a, int n_windows, size_t lds, hipStream_t s) {
     if (n_windows <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_cholesky, dim3(n_windows), dim3(64), lds, s, a);
+    hipLaunchKernelGGL(k_cholesky, dim3(n_windows), dim3(kCholThreads), lds, s, a);
     return hipGetLastError();
 }
 
@@ -145,13 +323,16 @@ __global__ __launch_bounds__(64) void k_decide(DecideArgs a) {
     Ctl *ctl = a.ctl + w;
     if (!ctl->running) return;
     const int lane = threadIdx.x;
+    double Ft = 0.0, den = 0.0, fl = 0.0;
+    for (int t = lane; t < W.ntiles; t += 64) {
+        Ft += a.partu[4 * (W.tile0 + t)];
+        den += a.partu[4 * (W.tile0 + t) + 1];
+        fl = fmax(fl, a.partu[4 * (W.tile0 + t) + 2]);
+    }
+    Ft = wave_sum(Ft);
+    den = wave_sum(den) + ctl->denom_p;
+    fl = wave_max(fl);
     if (lane == 0) {
-        double Ft = 0.0, den = ctl->denom_p, fl = 0.0;
-        for (int t = 0; t < W.ntiles; ++t) {
-            Ft += a.partu[4 * (W.tile0 + t)];
-            den += a.partu[4 * (W.tile0 + t) + 1];
-            fl = fmax(fl, a.partu[4 * (W.tile0 + t) + 2]);
-        }
         const int ok = ctl->solve_ok && fl == 0.0;
         const double gain = (ctl->F - Ft) / den;
         const int acc = ok && isfinite(Ft) && isfinite(gain) && gain > 0.0;
@@ -207,25 +388,36 @@ hipError_t launch_decide(const DecideArgs &a, int n_windows, hipStream_t s) {
 // damping initialisation of a round: F and lambda0 = tau * max diag(H)
 // ------------------------------------------------------------------------------------
 template <typename Real>
-__global__ __launch_bounds__(64) void k_init_reduce(InitReduceArgs a) {
+__global__ __launch_bounds__(256) void k_init_reduce(InitReduceArgs a) {
+    __shared__ double smax[4];
     const int w = blockIdx.x;
     const WinInfo W = a.win[w];
     Ctl *ctl = a.ctl + w;
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const Real *part = static_cast<const Real *>(a.part) + W.part_off;
+    // largest diagonal entry of Hpp (per camera, summed over the tiles) ...
     double md = 0.0;
-    for (int i = lane; i < W.n; i += 64) {
-        double acc = 0.0;
-        for (int t = 0; t < W.ntiles; ++t) acc += (double)part[(int64_t)t * W.part_stride + W.E + W.n + i];
-        md = fmax(md, acc);
-    }
-    md = wave_max(md);
-    if (lane == 0) {
-        double F = 0.0;
-        for (int t = 0; t < W.ntiles; ++t) {
-            F += a.partd[4 * (W.tile0 + t)];
-            md = fmax(md, a.partd[4 * (W.tile0 + t) + 1]);
+    for (int i = tid; i < W.n; i += blockDim.x) {
+        double s0 = 0.0, s1 = 0.0;
+        int t = 0;
+        for (; t + 1 < W.ntiles; t += 2) {
+            s0 += (double)part[(int64_t)t * W.part_stride + W.E + W.n + i];
+            s1 += (double)part[(int64_t)(t + 1) * W.part_stride + W.E + W.n + i];
         }
+        if (t < W.ntiles) s0 += (double)part[(int64_t)t * W.part_stride + W.E + W.n + i];
+        md = fmax(md, s0 + s1);
+    }
+    // ... and of the point blocks (per tile), and the cost
+    double F = 0.0;
+    for (int t = tid; t < W.ntiles; t += blockDim.x) md = fmax(md, a.partd[4 * (W.tile0 + t) + 1]);
+    if (wave == 0)
+        for (int t = lane; t < W.ntiles; t += 64) F += a.partd[4 * (W.tile0 + t)];
+    md = wave_max(md);
+    F = wave_sum(F);
+    if (lane == 0) smax[wave] = md;
+    __syncthreads();
+    if (tid == 0) {
+        md = fmax(fmax(smax[0], smax[1]), fmax(smax[2], smax[3]));
         if (a.round == 1) {
             ctl->F_initial = F;
         } else {
@@ -244,8 +436,8 @@ __global__ __launch_bounds__(64) void k_init_reduce(InitReduceArgs a) {
 
 hipError_t launch_init_reduce(const InitReduceArgs &a, int n_windows, hipStream_t s) {
     if (n_windows <= 0) return hipSuccess;
-    if (a.mixed) hipLaunchKernelGGL(k_init_reduce<float>, dim3(n_windows), dim3(64), 0, s, a);
-    else hipLaunchKernelGGL(k_init_reduce<double>, dim3(n_windows), dim3(64), 0, s, a);
+    if (a.mixed) hipLaunchKernelGGL(k_init_reduce<float>, dim3(n_windows), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_init_reduce<double>, dim3(n_windows), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -13,7 +13,7 @@ constexpr int kMaxObsPerPoint = 64;   // a point's observations fit one wavefron
 constexpr int kMaxKf = 128;           // keyframes per window (poses are staged in LDS)
 constexpr int kMaxLevels = 32;
 constexpr int kMaxKoptFP64 = 30;
-constexpr int kMaxKoptMixed = 40;
+constexpr int kMaxKoptMixed = 30;   // the FP64 reduced system must fit in LDS
 constexpr int kLinThreads = 256;      // 4 wavefronts per linearisation / update block
 
 // ------------------------------------------------------------------------------------
