@@ -10,7 +10,6 @@ namespace lba {
 // wavefronts sum the tiles t = g, g + 4, ... (g = wavefront) and the four partial sums
 // are combined in a fixed order, so the result does not depend on scheduling.
 // ------------------------------------------------------------------------------------
-template <typename Real>
 __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a) {
     __shared__ double acc4[4][64];
     const int w = blockIdx.y;
@@ -18,7 +17,7 @@ __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a) {
     if (!a.ctl[w].running) return;
     const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
     const int i = blockIdx.x * 64 + lane;
-    const int tot = W.E + 2 * W.n;
+    const int tot = W.E + W.n;
     if (blockIdx.x == 0 && g == 0) {
         // the window's point-block failure flag (written even when the system is empty)
         double fl = 0.0;
@@ -27,15 +26,23 @@ __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a) {
         if (lane == 0) a.redflag[w] = fl;
     }
     if (blockIdx.x * 64 >= tot) return;
-    const Real *part = static_cast<const Real *>(a.part) + W.part_off;
     double s0 = 0.0, s1 = 0.0;
-    if (i < tot) {
+    if (i < W.E) {
+        const double *part = a.part + W.part_off;
         int t = g;
         for (; t + 4 < W.ntiles; t += 8) {
-            s0 += (double)part[(int64_t)t * W.part_stride + i];
-            s1 += (double)part[(int64_t)(t + 4) * W.part_stride + i];
+            s0 += part[(int64_t)t * W.part_stride + i];
+            s1 += part[(int64_t)(t + 4) * W.part_stride + i];
         }
-        for (; t < W.ntiles; t += 4) s0 += (double)part[(int64_t)t * W.part_stride + i];
+        for (; t < W.ntiles; t += 4) s0 += part[(int64_t)t * W.part_stride + i];
+    } else if (i < tot) {
+        const double *pr = a.partr + W.partr_off + (i - W.E);
+        int t = g;
+        for (; t + 4 < W.ntiles; t += 8) {
+            s0 += pr[(int64_t)t * W.n];
+            s1 += pr[(int64_t)(t + 4) * W.n];
+        }
+        for (; t < W.ntiles; t += 4) s0 += pr[(int64_t)t * W.n];
     }
     acc4[g][lane] = s0 + s1;
     __syncthreads();
@@ -44,9 +51,8 @@ __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a) {
 
 hipError_t launch_reduce(const ReduceArgs &a, int n_windows, hipStream_t s) {
     if (n_windows <= 0) return hipSuccess;
-    dim3 grid((a.max_E2n + 63) / 64 > 0 ? (a.max_E2n + 63) / 64 : 1, n_windows), block(256);
-    if (a.mixed) hipLaunchKernelGGL(k_reduce<float>, grid, block, 0, s, a);
-    else hipLaunchKernelGGL(k_reduce<double>, grid, block, 0, s, a);
+    dim3 grid((a.max_En + 63) / 64 > 0 ? (a.max_En + 63) / 64 : 1, n_windows), block(256);
+    hipLaunchKernelGGL(k_reduce, grid, block, 0, s, a);
     return hipGetLastError();
 }
 
@@ -126,15 +132,15 @@ __global__ __launch_bounds__(kCholThreads) void k_cholesky(CholArgs a) {
     const int nth = blockDim.x;
     const double lambda = ctl->lambda;
     double *A = cs;          // E, packed lower
-    double *y = cs + E;      // n
-    double *bp = y + n;      // n
-    double *rdiag = bp + n;  // n reciprocal pivots
+    double *y = cs + E;      // n: right side, then the solution
+    double *rr = y + n;      // n: copy of the right side (gain-ratio denominator)
+    double *rdiag = rr + n;  // n reciprocal pivots
     double *Ld = rdiag + n;  // n x kNB: factored diagonal blocks (row r holds L[r][c0 .. r])
     const double *red = a.red + W.red_off;
     for (int i = tid; i < E; i += nth) A[i] = red[i];
     for (int i = tid; i < n; i += nth) {
         y[i] = red[E + i];
-        bp[i] = red[E + n + i];
+        rr[i] = red[E + i];
     }
     if (tid == 0) s_fail = a.redflag[w] != 0.0;
     __syncthreads();
@@ -297,7 +303,7 @@ __global__ __launch_bounds__(kCholThreads) void k_cholesky(CholArgs a) {
         for (int i = lane; i < n; i += 64) {
             const double x = ok ? y[i] : 0.0;
             dp[i] = x;
-            den += x * (lambda * x + bp[i]);
+            den += x * (lambda * x + rr[i]);   // + point part in the update kernel
         }
         den = wave_sum(den);
         if (lane == 0) {
@@ -387,24 +393,23 @@ hipError_t launch_decide(const DecideArgs &a, int n_windows, hipStream_t s) {
 // ------------------------------------------------------------------------------------
 // damping initialisation of a round: F and lambda0 = tau * max diag(H)
 // ------------------------------------------------------------------------------------
-template <typename Real>
 __global__ __launch_bounds__(256) void k_init_reduce(InitReduceArgs a) {
     __shared__ double smax[4];
     const int w = blockIdx.x;
     const WinInfo W = a.win[w];
     Ctl *ctl = a.ctl + w;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const Real *part = static_cast<const Real *>(a.part) + W.part_off;
     // largest diagonal entry of Hpp (per camera, summed over the tiles) ...
     double md = 0.0;
     for (int i = tid; i < W.n; i += blockDim.x) {
+        const double *pr = a.partr + W.partr_off + i;
         double s0 = 0.0, s1 = 0.0;
         int t = 0;
         for (; t + 1 < W.ntiles; t += 2) {
-            s0 += (double)part[(int64_t)t * W.part_stride + W.E + W.n + i];
-            s1 += (double)part[(int64_t)(t + 1) * W.part_stride + W.E + W.n + i];
+            s0 += pr[(int64_t)t * W.n];
+            s1 += pr[(int64_t)(t + 1) * W.n];
         }
-        if (t < W.ntiles) s0 += (double)part[(int64_t)t * W.part_stride + W.E + W.n + i];
+        if (t < W.ntiles) s0 += pr[(int64_t)t * W.n];
         md = fmax(md, s0 + s1);
     }
     // ... and of the point blocks (per tile), and the cost
@@ -436,8 +441,7 @@ __global__ __launch_bounds__(256) void k_init_reduce(InitReduceArgs a) {
 
 hipError_t launch_init_reduce(const InitReduceArgs &a, int n_windows, hipStream_t s) {
     if (n_windows <= 0) return hipSuccess;
-    if (a.mixed) hipLaunchKernelGGL(k_init_reduce<float>, dim3(n_windows), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(k_init_reduce<double>, dim3(n_windows), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_init_reduce, dim3(n_windows), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

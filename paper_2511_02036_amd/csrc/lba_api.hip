@@ -60,13 +60,14 @@ struct Plan {
     std::vector<int32_t> opt_map;
     std::vector<int32_t> kf_off, pt_off, obs_off;
     size_t lin_lds = 0, upd_lds = 0, chol_lds = 0;
-    int max_E2n = 0;
+    int max_En = 0;
     int64_t part_elems = 0;
+    int64_t partr_elems = 0;
     int64_t red_elems = 0;
     int64_t dp_elems = 0;
     // workspace byte offsets
     size_t o_win, o_tiles, o_opt, o_kfoff, o_ptoff, o_obsoff, o_upload_end;
-    size_t o_ptstart, o_ctl, o_T, o_X0, o_X1, o_part, o_partd, o_partu, o_red, o_redflag, o_dp,
+    size_t o_ptstart, o_ctl, o_T, o_X0, o_X1, o_part, o_partr, o_partd, o_partu, o_red, o_redflag, o_dp,
         o_stats, o_err, total;
 };
 
@@ -126,7 +127,7 @@ lba_status build_plan(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, Pl
     pl.win.resize(nw);
     pl.opt_map.assign(P->n_kf, -1);
     pl.tiles.clear();
-    int64_t part = 0, red = 0, dpo = 0;
+    int64_t part = 0, partr = 0, red = 0, dpo = 0;
     int maxK = 1, maxn = 0;
     for (int w = 0; w < nw; ++w) {
         WinInfo &W = pl.win[w];
@@ -162,35 +163,37 @@ lba_status build_plan(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, Pl
             T.pad = 0;
             pl.tiles.push_back(T);
         }
-        W.part_stride = W.E + 2 * W.n;
+        W.part_stride = W.E;
         W.part_off = part;
         part += W.part_stride * W.ntiles;
+        W.partr_off = partr;
+        partr += (int64_t)W.n * W.ntiles;
         W.red_off = (int32_t)red;
-        red += W.E + 2 * W.n;
+        red += W.E + W.n;
         W.dp_off = (int32_t)dpo;
         dpo += W.n;
         W.pad = 0;
         maxK = std::max(maxK, W.K);
         maxn = std::max(maxn, W.n);
-        pl.max_E2n = std::max(pl.max_E2n, W.E + 2 * W.n);
+        pl.max_En = std::max(pl.max_En, W.E + W.n);
     }
     if (red > INT32_MAX) return set_error(ctx, LBA_ERR_UNSUPPORTED, "batch too large");
     pl.part_elems = std::max<int64_t>(part, 1);
+    pl.partr_elems = std::max<int64_t>(partr, 1);
     pl.red_elems = std::max<int64_t>(red, 1);
     pl.dp_elems = std::max<int64_t>(dpo, 1);
 
-    // LDS: four wavefronts per block if the reduced system fits, fewer otherwise
+    // LDS: the update block uses four wavefronts if its staging fits, fewer otherwise
     pl.waves = 0;
     for (int wv = 4; wv >= 1; wv /= 2) {
-        if (lin_lds_bytes(maxK, maxn, wv, pl.mixed) <= (size_t)ctx->max_lds &&
-            upd_lds_bytes(maxK, maxn, wv, pl.mixed) <= (size_t)ctx->max_lds) {
+        if (upd_lds_bytes(maxK, maxn, wv, pl.mixed) <= (size_t)ctx->max_lds) {
             pl.waves = wv;
             break;
         }
     }
-    if (!pl.waves)
-        return set_error(ctx, LBA_ERR_UNSUPPORTED, "reduced system of %d unknowns does not fit in LDS", maxn);
-    pl.lin_lds = lin_lds_bytes(maxK, maxn, pl.waves, pl.mixed);
+    if (!pl.waves || lin_lds_bytes(maxK, maxn, 0, pl.mixed) > (size_t)ctx->max_lds)
+        return set_error(ctx, LBA_ERR_UNSUPPORTED, "window of %d keyframes does not fit in LDS", maxK);
+    pl.lin_lds = lin_lds_bytes(maxK, maxn, 0, pl.mixed);
     pl.upd_lds = upd_lds_bytes(maxK, maxn, pl.waves, pl.mixed);
     pl.chol_lds = chol_lds_bytes(maxn);
     if (pl.chol_lds > (size_t)ctx->max_lds)
@@ -205,13 +208,13 @@ lba_status build_plan(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, Pl
     pl.o_ptoff = o;  o = align256(o + sizeof(int32_t) * (nw + 1));
     pl.o_obsoff = o; o = align256(o + sizeof(int32_t) * (nw + 1));
     pl.o_upload_end = o;
-    const size_t real = pl.mixed ? sizeof(float) : sizeof(double);
     pl.o_ptstart = o; o = align256(o + sizeof(int32_t) * ((size_t)P->n_pt + 1));
     pl.o_ctl = o;     o = align256(o + sizeof(Ctl) * nw);
     pl.o_T = o;       o = align256(o + sizeof(double) * 12 * std::max(P->n_kf, 1));
     pl.o_X0 = o;      o = align256(o + sizeof(double) * 3 * std::max(P->n_pt, 1));
     pl.o_X1 = o;      o = align256(o + sizeof(double) * 3 * std::max(P->n_pt, 1));
-    pl.o_part = o;    o = align256(o + real * pl.part_elems);
+    pl.o_part = o;    o = align256(o + sizeof(double) * pl.part_elems);
+    pl.o_partr = o;   o = align256(o + sizeof(double) * pl.partr_elems);
     pl.o_partd = o;   o = align256(o + sizeof(double) * 4 * std::max<size_t>(pl.tiles.size(), 1));
     pl.o_partu = o;   o = align256(o + sizeof(double) * 4 * std::max<size_t>(pl.tiles.size(), 1));
     pl.o_red = o;     o = align256(o + sizeof(double) * pl.red_elems);
@@ -426,7 +429,8 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
     la.X1 = d_X1;
     la.ctl = d_ctl;
     la.obs = ob;
-    la.part = W_(pl.o_part);
+    la.part = static_cast<double *>(W_(pl.o_part));
+    la.partr = static_cast<double *>(W_(pl.o_partr));
     la.partd = d_partd;
     la.waves = pl.waves;
     la.c = c;
@@ -434,12 +438,12 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
     ReduceArgs ra;
     ra.win = d_win;
     ra.ctl = d_ctl;
-    ra.part = W_(pl.o_part);
+    ra.part = static_cast<const double *>(W_(pl.o_part));
+    ra.partr = static_cast<const double *>(W_(pl.o_partr));
     ra.partd = d_partd;
     ra.red = d_red;
     ra.redflag = d_redflag;
-    ra.max_E2n = pl.max_E2n;
-    ra.mixed = pl.mixed;
+    ra.max_En = pl.max_En;
 
     CholArgs ca;
     ca.win = d_win;
@@ -476,9 +480,8 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
     InitReduceArgs ia;
     ia.win = d_win;
     ia.ctl = d_ctl;
-    ia.part = W_(pl.o_part);
+    ia.partr = static_cast<const double *>(W_(pl.o_partr));
     ia.partd = d_partd;
-    ia.mixed = pl.mixed;
     ia.c = c;
 
     std::vector<Ctl> hctl(nw);

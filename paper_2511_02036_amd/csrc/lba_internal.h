@@ -14,7 +14,8 @@ constexpr int kMaxKf = 128;           // keyframes per window (poses are staged 
 constexpr int kMaxLevels = 32;
 constexpr int kMaxKoptFP64 = 30;
 constexpr int kMaxKoptMixed = 30;   // the FP64 reduced system must fit in LDS
-constexpr int kLinThreads = 256;      // 4 wavefronts per linearisation / update block
+constexpr int kLinThreads = 512;      // linearisation block (owner-computes reduced system)
+constexpr int kUpdThreads = 256;      // update block: 4 wavefronts
 
 // ------------------------------------------------------------------------------------
 // launch plan (built on the host, uploaded once per solve)
@@ -23,11 +24,12 @@ struct WinInfo {
     int32_t kf0, K, pt0, M, ob0, N;   // ranges in the concatenated arrays
     int32_t Kopt, n, E;               // optimisable kfs, n = 6 Kopt, E = n (n + 1) / 2
     int32_t tile0, ntiles;            // tiles of this window in the tile list
-    int32_t red_off;                  // doubles: reduced system (E + 2n) of this window
+    int32_t red_off;                  // doubles: reduced system (E + n) of this window
     int32_t dp_off;                   // doubles: pose step (n) of this window
     int32_t pad;
-    int64_t part_off;                 // Real elements: partial sums of tile 0
-    int64_t part_stride;              // Real elements per tile: E + 2n
+    int64_t part_off;                 // doubles: partial S (E per tile) of tile 0
+    int64_t part_stride;              // doubles per tile: E
+    int64_t partr_off;                // doubles: partial r (n per tile) of tile 0
 };
 
 struct Tile {
@@ -79,7 +81,8 @@ struct LinArgs {
     const Ctl *ctl;
     ObsView obs;
     const uint8_t *mask;         // round-2 outlier flags (1 = inactive) or nullptr
-    void *part;                  // Real partial sums per tile
+    double *part;                // partial S per tile (packed lower, FP64)
+    double *partr;               // FP64 partial r per tile (INIT: diagonal of Hpp)
     double *partd;               // 4 doubles per tile: F, max diag, fail, unused
     int robust;
     int waves;
@@ -89,12 +92,12 @@ struct LinArgs {
 struct ReduceArgs {
     const WinInfo *win;
     const Ctl *ctl;
-    const void *part;
+    const double *part;
+    const double *partr;
     const double *partd;
-    double *red;                 // per window: E packed-lower S, n r, n bp, then fail flag
+    double *red;                 // per window: E packed-lower S, then n r
     double *redflag;             // per window fail flag
-    int max_E2n;
-    int mixed;
+    int max_En;
 };
 
 struct CholArgs {
@@ -116,7 +119,7 @@ struct UpdArgs {
     const double *dp;
     ObsView obs;
     const uint8_t *mask;
-    double *partu;               // 4 doubles per tile: F', denominator, fail, unused
+    double *partu;               // 4 doubles per tile: F', denominator part, fail, unused
     int robust;
     int waves;
     SolveConsts c;
@@ -136,10 +139,9 @@ struct DecideArgs {
 struct InitReduceArgs {
     const WinInfo *win;
     Ctl *ctl;
-    const void *part;
+    const double *partr;
     const double *partd;
     int round;
-    int mixed;
     SolveConsts c;
 };
 
@@ -395,6 +397,52 @@ __device__ __forceinline__ void obs_blocks(const CamParams &cam, const double *T
         B.M[2 * 3 + c] = G02 * r0 + G12 * r1 + G22 * r2;
     }
     B.x[0] = x; B.x[1] = y; B.x[2] = z;
+}
+
+// gradient piece g = om P^T e of an observation in FP64 (P = d pi / d Xc)
+__device__ __forceinline__ void obs_gradient(const CamParams &cam, double xc, double yc, double zc, double eu,
+                                             double ev, double er, int stereo, double om, double *g) {
+    const double iz = 1.0 / zc, st = stereo ? 1.0 : 0.0;
+    const double p00 = cam.fx * iz, p02 = -cam.fx * xc * iz * iz;
+    const double p11 = cam.fy * iz, p12 = -cam.fy * yc * iz * iz;
+    const double p22 = -(cam.fx * xc - cam.bf) * iz * iz;
+    g[0] = om * (p00 * eu + st * p00 * er);
+    g[1] = om * (p11 * ev);
+    g[2] = om * (p02 * eu + p12 * ev + st * p22 * er);
+}
+
+// point block of an observation in FP64: Hll = R^T G R (6 upper entries) and bl = R^T g,
+// G = om P^T P, g = om P^T e.  The 3x3 point blocks are factored in FP64 in every
+// precision: a point left with one monocular observation has a rank-2 Hll, so V = Hll +
+// lambda I is conditioned like max(Hll) / lambda and loses its small pivot in FP32.
+__device__ __forceinline__ void point_block_fp64(const CamParams &cam, const double *T, double xc, double yc,
+                                                 double zc, double eu, double ev, double er, int stereo,
+                                                 double om, double *Hll, double *bl) {
+    const double iz = 1.0 / zc, st = stereo ? 1.0 : 0.0;
+    const double p00 = cam.fx * iz, p02 = -cam.fx * xc * iz * iz;
+    const double p11 = cam.fy * iz, p12 = -cam.fy * yc * iz * iz;
+    const double p22 = -(cam.fx * xc - cam.bf) * iz * iz;
+    const double G00 = om * (p00 * p00 * (1.0 + st)), G02 = om * (p00 * p02 + st * p00 * p22);
+    const double G11 = om * (p11 * p11), G12 = om * (p11 * p12);
+    const double G22 = om * (p02 * p02 + p12 * p12 + st * p22 * p22);
+    const double g0 = om * (p00 * eu + st * p00 * er), g1 = om * (p11 * ev);
+    const double g2 = om * (p02 * eu + p12 * ev + st * p22 * er);
+    double M[9];   // G R
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double r0 = T[c], r1 = T[4 + c], r2 = T[8 + c];
+        M[c] = G00 * r0 + G02 * r2;
+        M[3 + c] = G11 * r1 + G12 * r2;
+        M[6 + c] = G02 * r0 + G12 * r1 + G22 * r2;
+    }
+    Hll[0] = T[0] * M[0] + T[4] * M[3] + T[8] * M[6];
+    Hll[1] = T[0] * M[1] + T[4] * M[4] + T[8] * M[7];
+    Hll[2] = T[0] * M[2] + T[4] * M[5] + T[8] * M[8];
+    Hll[3] = T[1] * M[1] + T[5] * M[4] + T[9] * M[7];
+    Hll[4] = T[1] * M[2] + T[5] * M[5] + T[9] * M[8];
+    Hll[5] = T[2] * M[2] + T[6] * M[5] + T[10] * M[8];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) bl[i] = T[i] * g0 + T[4 + i] * g1 + T[8 + i] * g2;
 }
 
 // Hll (6 upper entries) and bl of an observation

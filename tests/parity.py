@@ -72,3 +72,40 @@ def window_slice(cat, i):
     p0, p1 = cat["pt_off"][i], cat["pt_off"][i + 1]
     o0, o1 = cat["obs_off"][i], cat["obs_off"][i + 1]
     return slice(k0, k1), slice(p0, p1), slice(o0, o1)
+
+
+def pose_errors(T_a, T_b):
+    """Largest camera-centre distance (m) and rotation angle (rad) between two pose sets."""
+    A = np.asarray(T_a).reshape(-1, 3, 4)
+    B = np.asarray(T_b).reshape(-1, 3, 4)
+    ca = -np.einsum("kji,kj->ki", A[:, :, :3], A[:, :, 3])
+    cb = -np.einsum("kji,kj->ki", B[:, :, :3], B[:, :, 3])
+    dpos = np.linalg.norm(ca - cb, axis=1).max(initial=0.0)
+    Rr = np.einsum("kij,klj->kil", A[:, :, :3], B[:, :, :3])
+    # angle from both the skew and the symmetric part (arccos alone loses digits near 0)
+    sk = np.stack([Rr[:, 2, 1] - Rr[:, 1, 2], Rr[:, 0, 2] - Rr[:, 2, 0], Rr[:, 1, 0] - Rr[:, 0, 1]], axis=1)
+    ang = np.arctan2(0.5 * np.linalg.norm(sk, axis=1), 0.5 * (np.trace(Rr, axis1=1, axis2=2) - 1.0))
+    return float(dpos), float(np.abs(ang).max(initial=0.0))
+
+
+def mixed_metrics(w, g_T, g_X, g_stats, ref):
+    """Errors of a mixed-precision (or batched) solve against the FP64 oracle."""
+    Fr = ref["stats"]["F_final"]
+    rel = abs(g_stats["F_final"] - Fr) / max(abs(Fr), 1e-30)
+    rms = reprojection_rms_diff(w, g_T, g_X, ref["T"], ref["X"], ~ref["outlier"])
+    dpos, dang = pose_errors(g_T, ref["T"])
+    return dict(cost_rel=rel, rms_px=rms, pos_m=dpos, rot_rad=dang)
+
+
+def assert_mixed_tolerances(w, g_T, g_X, g_stats, ref, cost_rel=1e-4, rms_px=0.01):
+    m = mixed_metrics(w, g_T, g_X, g_stats, ref)
+    assert m["cost_rel"] <= cost_rel, m
+    assert m["rms_px"] <= rms_px, m
+    return m
+
+
+def round_z_f32(w):
+    """The window with its measurements rounded to FP32 (what an FP32 upload holds)."""
+    out = dict(w)
+    out["obs_z"] = w["obs_z"].astype(np.float32).astype(np.float64)
+    return out

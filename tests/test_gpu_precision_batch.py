@@ -1,0 +1,110 @@
+"""Mixed-precision form (FP32 Jacobians / Hessian blocks / Schur, FP64 Cholesky, cost,
+gain ratio, damping and states) and the batched form (many uneven windows per launch),
+against the FP64 CPU oracle."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import lbaref
+from paper_2511_02036_amd import synth
+from tests.parity import (assert_fp64_parity, assert_mixed_tolerances, mixed_metrics, round_z_f32,
+                          window_slice)
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2511_02036_amd import lba  # noqa: E402
+
+OUT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+
+
+def _record(name, value):
+    os.makedirs(OUT, exist_ok=True)
+    with open(os.path.join(OUT, "precision_metrics.jsonl"), "a") as f:
+        f.write(json.dumps({"case": name, **value}) + "\n")
+
+
+@pytest.mark.parametrize("seed", [40, 41, 42])
+def test_mixed_small_windows(seed):
+    w = synth.tiny_window(seed, K=8, n_fixed=3, M=400, nobs=(3, 8), stereo_p=0.7)
+    g = lba.solve(w, device="cuda:0", precision="mixed")
+    r = lbaref.solve(w)
+    assert_mixed_tolerances(w, g["T"], g["X"], g["stats"][0], r)
+
+
+@pytest.mark.parametrize("z_f32", [False, True])
+def test_mixed_c2(z_f32):
+    w = synth.c2_stereo()
+    wr = round_z_f32(w) if z_f32 else w
+    g = lba.solve(w, device="cuda:0", precision="mixed", z_f32=z_f32)
+    r = lbaref.solve(wr)
+    m = assert_mixed_tolerances(wr, g["T"], g["X"], g["stats"][0], r)
+    _record(f"c2_mixed_zf32={z_f32}", m)
+
+
+def test_mixed_c3_precision_form():
+    w = synth.c3_precision()
+    print(f"case c3 N={len(w['obs_kf'])}", flush=True)
+    wr = round_z_f32(w)
+    g = lba.solve(w, device="cuda:0", precision="mixed", z_f32=True)
+    r = lbaref.solve(wr)
+    m = assert_mixed_tolerances(wr, g["T"], g["X"], g["stats"][0], r)
+    m["flags_differ"] = int((g["outlier"] != r["outlier"]).sum())
+    _record("c3_mixed", m)
+
+
+def test_fp64_c3_matches_oracle():
+    """The largest reduced system (180 unknowns) also runs in FP64 at oracle parity."""
+    w = synth.c3_precision()
+    g = lba.solve(w, device="cuda:0")
+    r = lbaref.solve(w)
+    assert_fp64_parity(w, g["T"], g["X"], g["outlier"], g["stats"][0], r)
+
+
+def test_fp64_batch_of_c5_shaped_windows_matches_oracle():
+    ws = synth.c5_windows(only=list(range(12)), max_points=1500)
+    cat = synth.concat(ws)
+    g = lba.solve(cat, device="cuda:0")
+    for i, w in enumerate(ws):
+        ks, ps, os_ = window_slice(cat, i)
+        r = lbaref.solve(w)
+        assert_fp64_parity(w, g["T"][ks], g["X"][ps], g["outlier"][os_], g["stats"][i], r)
+
+
+def test_batch_equals_one_window_at_a_time():
+    ws = synth.c5_windows(only=[3, 7, 11, 19], max_points=3000)
+    cat = synth.concat(ws)
+    g = lba.solve(cat, device="cuda:0")
+    for i, w in enumerate(ws):
+        ks, ps, os_ = window_slice(cat, i)
+        s = lba.solve(w, device="cuda:0")
+        np.testing.assert_allclose(g["T"][ks], s["T"], rtol=0, atol=1e-10)
+        np.testing.assert_allclose(g["X"][ps], s["X"], rtol=0, atol=1e-9)
+        assert g["stats"][i]["F_final"] == pytest.approx(s["stats"][0]["F_final"], rel=1e-11)
+
+
+@pytest.fixture(scope="module")
+def c5():
+    ws = synth.c5_windows()
+    return ws, synth.concat(ws)
+
+
+def test_c5_full_batch_mixed_sampled_windows(c5):
+    ws, cat = c5
+    print(f"case c5 windows={len(ws)} N={len(cat['obs_kf'])}", flush=True)
+    g = lba.solve(cat, device="cuda:0", precision="mixed", z_f32=True)
+    st = g["stats"]
+    assert all(s["iters_r1"] >= 1 and s["iters_r2"] >= 1 for s in st)
+    Ns = np.diff(cat["obs_off"])
+    sample = sorted({int(np.argmin(Ns)), int(np.argsort(Ns)[len(Ns) // 2]), int(np.argmax(Ns))})
+    for i in sample:
+        ks, ps, os_ = window_slice(cat, i)
+        wr = round_z_f32(ws[i])
+        r = lbaref.solve(wr)
+        m = assert_mixed_tolerances(wr, g["T"][ks], g["X"][ps], st[i], r)
+        _record(f"c5_mixed_window{i}_N{int(Ns[i])}", m)
