@@ -54,6 +54,11 @@ WORKLOADS = {
         desc="plain FP64 monocular local BA, seed 0: 10 optimisable + 5 fixed keyframes on a 2 m arc, "
              "1,500 points, 8 observations per point, 5+10 LM iterations",
         precision="fp64", z_f32=False, compare_plain=False),
+    "c4_differentiation": dict(
+        desc="differentiation form, seed 3: 64 windows of 10 keyframes and 2,000 points, 8 observations "
+             "per point, even windows monocular, odd 70/30 stereo/mono; one step = FP32 robust-cost "
+             "forward + hand-written backward (gradients for poses, points, measurements) of all windows",
+        precision="fp64", z_f32=True, compare_plain=False),
     "c3_precision_mixed": dict(
         desc="precision form, seed 2: 30 optimisable + 20 fixed stereo keyframes, 20,000 points, "
              "10 observations per point, FP32 bulk + FP64 reduced solve, 5+10 LM iterations",
@@ -71,6 +76,8 @@ def make_windows(name):
         return [synth.c1_mono(seed=0)]
     if name.startswith("c3"):
         return [synth.c3_precision(seed=2)]
+    if name.startswith("c4"):
+        return synth.c4_windows(seed=3)
     raise ValueError(name)
 
 
@@ -169,6 +176,78 @@ def cpu_baseline(windows, budget_s=12.0):
                        f"thread on {cores} threads, {el:.1f} s"), dict(zip(sample, res))
 
 
+def cost_layer_bytes(cls, windows):
+    """Algorithmic bytes and flops of one launch of the robust-cost layer over all windows:
+    forward reads each observation record (22 B) and each point (12 B); backward also
+    writes 12 B of measurement gradient per observation and 12 B of point gradient per
+    point.  Flops: ~45 per observation forward, ~110 backward (counted from the kernel)."""
+    N = sum(len(w["obs_kf"]) for w in windows)
+    M = sum(len(w["X"]) for w in windows)
+    if cls == "cost_forward":
+        return N * 22 + M * 16, 45 * N
+    return N * 34 + M * 28, 110 * N
+
+
+def bench_cost_layer(args, spec):
+    """One step = forward + backward of the robust-cost layer over every window."""
+    import numpy as np
+    import torch
+    from paper_2511_02036_amd import lba, synth
+    windows = make_windows(args.workload)
+    cat = synth.concat(windows)
+    dev = torch.device("cuda:0")
+    ctx = lba.Context(device=0, check_inputs=0)
+    layer = lba.CostLayer(ctx, cat, device=dev)
+    X = torch.tensor(np.asarray(cat["X"], dtype=np.float32).reshape(-1, 3), device=dev)
+    z = torch.tensor(np.asarray(cat["obs_z"], dtype=np.float32).reshape(3, -1), device=dev)
+    xi = torch.zeros((layer.n_kf, 6), dtype=torch.float32, device=dev)
+    g = torch.ones(layer.n_windows, dtype=torch.float64, device=dev)
+    def step():
+        layer.forward(xi, X, z)
+        layer.backward(xi, X, z, g)
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    steps = max(args.steps, 1) * 20
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    kern = {k: dict(launches=n, mean_us=(1e3 * ms / n if n else 0.0)) for k, (n, ms) in prof.items() if n}
+    b, f = cost_layer_bytes("cost_backward", windows)
+    mb = kern["cost_backward"]["mean_us"] * 1e-6
+    roof = dict(kernel="cost_backward", bound="hbm", achieved=b / mb / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=b / mb / 1e9 / HBM_PEAK_GBS, traffic=None, bytes_per_launch=b, mean_us=kern["cost_backward"]["mean_us"],
+                alu_TFLOPs=f / mb / 1e12)
+    nw = len(windows)
+    out = {"metric": METRIC, "value": nw * steps / el, "unit": "window-cost-gradients/s", "n_gpus": 1,
+           "steps": steps, "warmup": args.warmup, "ms_per_step": 1e3 * el / steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": args.workload, "description": spec["desc"], "windows": nw,
+                      "observations": int(sum(len(w["obs_kf"]) for w in windows)),
+                      "points": int(sum(len(w["X"]) for w in windows))},
+           "roofline": roof, "kernels_us_mean": {k: round(v["mean_us"], 2) for k, v in kern.items()}}
+    if not args.no_cpu_baseline:
+        from oracle import lbaref
+        t0 = time.perf_counter()
+        n = 0
+        while True:
+            lbaref.cost_grad(windows[n % nw])
+            n += 1
+            if time.perf_counter() - t0 >= 10.0:
+                break
+        el = time.perf_counter() - t0
+        out["cpu_baseline"] = dict(value=n / el, unit="window-cost-gradients/s", cores=1, kind="oracle",
+                                   sample=f"{n} FP64 cost + gradient evaluations of the workload's windows "
+                                          f"in {el:.1f} s, one thread")
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -177,6 +256,9 @@ def main():
     ap.add_argument("--workload", default="c5_batched_mixed", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-window plain FP64 comparison")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy 256 MiB device to device once (a kernel of known traffic that "
+                         "calibrates hardware byte counters read by a profiler)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -191,6 +273,15 @@ def main():
     from paper_2511_02036_amd import lba, synth
 
     spec = WORKLOADS[args.workload]
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    if args.workload.startswith("c4"):
+        bench_cost_layer(args, spec)
+        return
     t_gen = time.perf_counter()
     windows = make_windows(args.workload)
     data = windows[0] if len(windows) == 1 else synth.concat(windows)

@@ -67,14 +67,18 @@ typedef struct {
     int32_t iters_round2;    /* LM iterations after it [10] */
     int32_t max_trials;      /* damped solves per iteration before the round ends [10] */
     int32_t round2_robust;   /* 1: keep the Huber kernel in round 2, 0: plain squares [1] */
-    int32_t check_inputs;    /* 1: validate indices/octaves/sortedness on the GPU first [1] */
+    int32_t check_inputs;    /* cost layer: 1 = validate indices/octaves/order on the GPU first
+                                [1]; the solver always validates */
     double huber2_mono;      /* Huber threshold on s, monocular [5.991] */
     double huber2_stereo;    /* Huber threshold on s, stereo [7.815] */
     double chi2_mono;        /* outlier threshold on s, monocular [5.991] */
     double chi2_stereo;      /* outlier threshold on s, stereo [7.815] */
     double tau;              /* initial damping factor [1e-5] */
-    int32_t points_per_tile; /* 0: chosen by the library's tile tuner; else fixed */
-    int32_t reserved;
+    int32_t points_per_tile; /* 0: per window from lba_tune's table for this problem if it
+                                was tuned, else from the total point count; else fixed */
+    int32_t use_graphs;      /* 1: each LM step (five kernels over every window) is captured
+                                once into a HIP graph and replayed; kernels are launched one
+                                by one while profiling is enabled [1] */
 } lba_options;
 
 typedef struct {
@@ -177,6 +181,19 @@ lba_status lba_solve_batch(lba_ctx *ctx, const lba_problem *problem, const lba_b
                            lba_result *result, void *workspace, size_t workspace_bytes,
                            void *stream);
 
+/* Tile tuner of the batched form.  The linearisation and update kernels run one block per
+ * tile of consecutive points of a window; the tile size trades per-tile work (the partial
+ * reduced system each tile writes and the fixed-order sum over tiles) against the number
+ * of blocks that fill the GPU.  lba_tune times short solves (three LM steps on every
+ * window, on `stream`) of this problem with candidate tile sizes 64 ... 4096 points, one
+ * value per class of windows by optimisable keyframes (<= 10, <= 20, > 20), by coordinate
+ * descent, and keeps the fastest table in the context: later solves of a problem with the
+ * same sizes and precision use it when points_per_tile is 0.  The problem's inputs are
+ * only read.  It allocates and frees its own device scratch (hipMalloc) and synchronises
+ * the stream; points_per_tile (HOST, 3 entries, or NULL) receives the table. */
+lba_status lba_tune(lba_ctx *ctx, const lba_problem *problem, const lba_batch *batch, void *stream,
+                    int32_t *points_per_tile);
+
 /* ---- per-kernel timing ------------------------------------------------------------------
  * With profiling enabled, every kernel a solve launches is bracketed by two HIP events on
  * the caller's stream and, at the end of the solve, its duration is added to the counters
@@ -194,11 +211,55 @@ typedef enum {
     LBA_KCLASS_VALIDATE,
     LBA_KCLASS_FLAGS,            /* chi-square outlier pass */
     LBA_KCLASS_FINALIZE,
+    LBA_KCLASS_COST_FORWARD,     /* robust-cost layer, forward */
+    LBA_KCLASS_COST_BACKWARD,    /* robust-cost layer, backward */
     LBA_KCLASS_COUNT
 } lba_kernel_class;
 
 lba_status lba_profile_enable(lba_ctx *ctx, int32_t enable);
 lba_status lba_profile_read(const lba_ctx *ctx, int32_t kernel_class, int64_t *launches, double *total_ms);
+
+/* ---- differentiation form: the robust reprojection cost as a layer ----------------------
+ * The same cost the solver minimises (Section III-C: reprojection residuals of the local
+ * keyframes and their points), as a differentiable function of the poses, points and
+ * measurements of every window of a batch:
+ *
+ *   cost[w] = sum over the observations i of window w not masked out of rho(s_i),
+ *   s_i = |z_i - pi(Exp(xi_k) T_k X_j)|^2 / sigma2[octave_i],
+ *
+ * with rho the Huber function on s (huber2_mono / huber2_stereo of the context's
+ * options), pi the mono or stereo projection and Exp(xi) the SE(3) exponential of a
+ * left perturbation xi = (rotation, translation) of the base pose T_k (xi NULL: zero).
+ * The backward pass returns, for an upstream gradient grad_cost[w],
+ *   g_xi[k] = dL/dxi_k      (all keyframes, fixed or not: the fixed mask is not read),
+ *   g_X[j]  = dL/dX_j,      g_z[i] = dL/dz_i   (zero for masked observations and for the
+ *                                                uR row of monocular observations).
+ * Per-observation arithmetic is FP32; the cost and the pose-gradient sums accumulate in
+ * FP64 in a fixed order, so results are reproducible bit for bit.  The backward pass
+ * recomputes the Jacobians from the inputs; nothing is kept between the two calls.
+ *
+ * Topology and constants come from `problem` (and `batch`, NULL: one window):
+ * n_kf, n_pt, n_obs, n_levels, T_cw (DEVICE, FP64 base poses), obs_kf, obs_pt, obs_type,
+ * obs_oct (DEVICE), sigma2 (HOST), cam.  problem->X_w, obs_z and fixed are not read: the
+ * differentiable inputs are the separate FP32 arrays
+ *   xi   DEVICE n_kf x 6 or NULL,   X   DEVICE n_pt x 3,   z   DEVICE 3 x n_obs planar
+ *   mask DEVICE n_obs (1 = observation left out) or NULL.
+ * Outputs (DEVICE, caller-owned): cost n_windows doubles; g_xi n_kf x 6, g_X n_pt x 3,
+ * g_z 3 x n_obs floats, every entry written.  grad_cost is DEVICE n_windows doubles.
+ * Limits: n_kf <= 128 per window, at most 64 observations per point.  With
+ * check_inputs set (the default) the indices are validated on the GPU first and the
+ * stream is synchronised once to read the verdict (LBA_ERR_INVALID_ARGUMENT on a bad
+ * index, octave, type or order); with it off nothing synchronises, and invalid indices
+ * are skipped by the kernels and leave the outputs undefined. */
+lba_status lba_cost_workspace_size(lba_ctx *ctx, const lba_problem *problem, const lba_batch *batch,
+                                   size_t *bytes);
+lba_status lba_cost_forward(lba_ctx *ctx, const lba_problem *problem, const lba_batch *batch,
+                            const float *xi, const float *X, const float *z, const uint8_t *mask,
+                            double *cost, void *workspace, size_t workspace_bytes, void *stream);
+lba_status lba_cost_backward(lba_ctx *ctx, const lba_problem *problem, const lba_batch *batch,
+                             const float *xi, const float *X, const float *z, const uint8_t *mask,
+                             const double *grad_cost, float *g_xi, float *g_X, float *g_z,
+                             void *workspace, size_t workspace_bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -20,13 +20,16 @@ enum : int32_t {
     ERR_TOO_MANY_OBS = 256, ERR_STEREO_NO_BASELINE = 512
 };
 
-// copy the inputs into the working state and reset the control blocks
+// copy the inputs into the working state and reset the control blocks (each of these
+// steps is skipped when its destination is null), then the point -> observation offsets
 __global__ void k_setup(MiscArgs a) {
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nth = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = tid; i < (int64_t)a.n_kf * 12; i += nth) a.T[i] = a.T_in[i];
-    for (int64_t i = tid; i < (int64_t)a.n_pt * 3; i += nth) a.X0[i] = a.X_in[i];
-    for (int64_t w = tid; w < a.c.n_windows; w += nth) {
+    if (a.T)
+        for (int64_t i = tid; i < (int64_t)a.n_kf * 12; i += nth) a.T[i] = a.T_in[i];
+    if (a.X0)
+        for (int64_t i = tid; i < (int64_t)a.n_pt * 3; i += nth) a.X0[i] = a.X_in[i];
+    for (int64_t w = tid; a.ctl && w < a.c.n_windows; w += nth) {
         Ctl c;
         c.lambda = 0.0; c.nu = 2.0; c.F = 0.0; c.F_trial = 0.0; c.denom_p = 0.0;
         c.F_initial = 0.0; c.F_end_r1 = 0.0; c.F_start_r2 = 0.0;
@@ -81,10 +84,12 @@ __global__ void k_validate(MiscArgs a) {
         else load_z<double>(a.obs, (int)o, u, v, ur);
         if (!isfinite(u) || !isfinite(v) || (ty == 1 && !isfinite(ur))) err |= ERR_NONFINITE_OBS;
     }
-    for (int64_t i = tid; i < (int64_t)a.n_kf * 12; i += nth)
-        if (!isfinite(a.T_in[i])) err |= ERR_NONFINITE_POSE;
-    for (int64_t i = tid; i < (int64_t)a.n_pt * 3; i += nth)
-        if (!isfinite(a.X_in[i])) err |= ERR_NONFINITE_POINT;
+    if (a.T_in)
+        for (int64_t i = tid; i < (int64_t)a.n_kf * 12; i += nth)
+            if (!isfinite(a.T_in[i])) err |= ERR_NONFINITE_POSE;
+    if (a.X_in)
+        for (int64_t i = tid; i < (int64_t)a.n_pt * 3; i += nth)
+            if (!isfinite(a.X_in[i])) err |= ERR_NONFINITE_POINT;
     for (int64_t p = tid; p < a.n_pt; p += nth)
         if (a.pt_start[p + 1] - a.pt_start[p] > kMaxObsPerPoint) err |= ERR_TOO_MANY_OBS;
     if (err) atomicOr(a.err, err);

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -22,6 +23,20 @@ struct lba_ctx {
     std::string err;
     void *pinned = nullptr;
     size_t pinned_bytes = 0;
+    hipEvent_t upload_ev = nullptr;   // recorded after the last copy out of `pinned`
+    bool upload_pending = false;
+    // LM-step graphs: captured on a private stream, replayed on the caller's
+    hipStream_t cap_stream = nullptr;
+    struct GraphEntry {
+        std::string key;
+        hipGraph_t graph;
+        hipGraphExec_t exec;
+    };
+    std::vector<GraphEntry> graphs;   // most recently used last
+    // tile tuner: points per tile by optimisable-keyframe class (Kopt <= 10, <= 20, > 20)
+    int64_t tuned_sig[5] = {-1, -1, -1, -1, -1};
+    int tuned_ppt[3] = {0, 0, 0};
+    const int *ppt_override = nullptr;   // set while the tuner measures a candidate
     // kernel timing
     bool prof = false;
     std::vector<hipEvent_t> ev_pool;
@@ -50,6 +65,8 @@ lba_status set_error(lba_ctx *ctx, lba_status st, const char *fmt, ...) {
     } while (0)
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+constexpr size_t kGraphCache = 8;
 
 struct Plan {
     int nw = 0;
@@ -80,6 +97,24 @@ int choose_points_per_tile(const lba_options &opt, int64_t total_points) {
     p = (p + 31) / 32 * 32;
     p = std::max<int64_t>(64, std::min<int64_t>(4096, p));
     return (int)p;
+}
+
+int kopt_class(int kopt) { return kopt <= 10 ? 0 : (kopt <= 20 ? 1 : 2); }
+
+void tune_signature(const lba_problem *P, int nw, bool mixed, int64_t *sig) {
+    sig[0] = P->n_kf;
+    sig[1] = P->n_pt;
+    sig[2] = P->n_obs;
+    sig[3] = nw;
+    sig[4] = mixed ? 1 : 0;
+}
+
+bool tune_signature_matches(const lba_ctx *ctx, const lba_problem *P, int nw, bool mixed) {
+    int64_t sig[5];
+    tune_signature(P, nw, mixed, sig);
+    for (int i = 0; i < 5; ++i)
+        if (sig[i] != ctx->tuned_sig[i]) return false;
+    return true;
 }
 
 lba_status build_plan(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, Plan &pl) {
@@ -122,7 +157,12 @@ lba_status build_plan(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, Pl
         return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "batch offsets must start at 0 and end at the totals");
 
     int64_t total_points = P->n_pt;
-    const int ppt = choose_points_per_tile(opt, total_points);
+    const int ppt_default = choose_points_per_tile(opt, total_points);
+    const int *class_ppt = nullptr;
+    if (opt.points_per_tile <= 0) {
+        if (ctx->ppt_override) class_ppt = ctx->ppt_override;
+        else if (tune_signature_matches(ctx, P, nw, pl.mixed)) class_ppt = ctx->tuned_ppt;
+    }
     const int kopt_max = pl.mixed ? kMaxKoptMixed : kMaxKoptFP64;
     pl.win.resize(nw);
     pl.opt_map.assign(P->n_kf, -1);
@@ -153,6 +193,7 @@ lba_status build_plan(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, Pl
         W.Kopt = kopt;
         W.n = 6 * kopt;
         W.E = W.n * (W.n + 1) / 2;
+        const int ppt = class_ppt ? class_ppt[kopt_class(kopt)] : ppt_default;
         W.tile0 = (int)pl.tiles.size();
         W.ntiles = (W.M + ppt - 1) / ppt;
         for (int t = 0; t < W.ntiles; ++t) {
@@ -226,7 +267,26 @@ lba_status build_plan(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, Pl
     return LBA_OK;
 }
 
+// the pinned staging buffer is reused by every call: wait until the copy that the
+// previous call enqueued from it has been executed
+lba_status wait_upload(lba_ctx *ctx) {
+    if (ctx->upload_pending) {
+        HIPCHK(hipEventSynchronize(ctx->upload_ev));
+        ctx->upload_pending = false;
+    }
+    return LBA_OK;
+}
+
+lba_status record_upload(lba_ctx *ctx, hipStream_t s) {
+    if (!ctx->upload_ev) HIPCHK(hipEventCreateWithFlags(&ctx->upload_ev, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(ctx->upload_ev, s));
+    ctx->upload_pending = true;
+    return LBA_OK;
+}
+
 lba_status ensure_pinned(lba_ctx *ctx, size_t bytes) {
+    lba_status st = wait_upload(ctx);
+    if (st != LBA_OK) return st;
     if (ctx->pinned_bytes >= bytes) return LBA_OK;
     if (ctx->pinned) HIPCHK(hipHostFree(ctx->pinned));
     ctx->pinned = nullptr;
@@ -304,6 +364,48 @@ hipError_t collect_timing(lba_ctx *ctx) {
     return hipSuccess;
 }
 
+// executable graph of one LM step for the launch arguments `key`: captured from `step` on
+// the context's private stream the first time (nothing runs during a capture) and kept in
+// a small cache, most recently used last
+template <typename Fn>
+lba_status step_graph(lba_ctx *ctx, const std::string &key, Fn &&step, hipGraphExec_t *out) {
+    auto &G = ctx->graphs;
+    for (size_t i = 0; i < G.size(); ++i)
+        if (G[i].key == key) {
+            lba_ctx::GraphEntry e = G[i];
+            G.erase(G.begin() + i);
+            G.push_back(e);
+            *out = e.exec;
+            return LBA_OK;
+        }
+    if (!ctx->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    HIPCHK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+    const hipError_t le = step(ctx->cap_stream);
+    const hipError_t ce = hipStreamEndCapture(ctx->cap_stream, &graph);
+    if (le != hipSuccess || ce != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return set_error(ctx, LBA_ERR_HIP, "capture of the LM step failed: %s",
+                         hipGetErrorString(le != hipSuccess ? le : ce));
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return set_error(ctx, LBA_ERR_HIP, "hipGraphInstantiate failed: %s", hipGetErrorString(ie));
+    }
+    if (G.size() >= kGraphCache) {
+        // every solve synchronises its stream before it returns, so only the current
+        // solve's graphs (the newest entries) can still be pending
+        (void)hipGraphExecDestroy(G.front().exec);
+        (void)hipGraphDestroy(G.front().graph);
+        G.erase(G.begin());
+    }
+    G.push_back({key, graph, exec});
+    *out = exec;
+    return LBA_OK;
+}
+
 lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lba_result *R, void *ws,
                       size_t ws_bytes, void *stream_ptr) {
     if (!ctx) return LBA_ERR_INVALID_ARGUMENT;
@@ -342,6 +444,8 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
     memcpy(up + pl.o_ptoff, pl.pt_off.data(), sizeof(int32_t) * (nw + 1));
     memcpy(up + pl.o_obsoff, pl.obs_off.data(), sizeof(int32_t) * (nw + 1));
     HIPCHK(hipMemcpyAsync(wsb, up, pl.o_upload_end, hipMemcpyHostToDevice, s));
+    st = record_upload(ctx, s);
+    if (st != LBA_OK) return st;
 
     // ---- constants and argument packs ----------------------------------------------------
     SolveConsts c;
@@ -436,6 +540,7 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
     la.c = c;
 
     ReduceArgs ra;
+    memset(&ra, 0, sizeof(ra));
     ra.win = d_win;
     ra.ctl = d_ctl;
     ra.part = static_cast<const double *>(W_(pl.o_part));
@@ -446,6 +551,7 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
     ra.max_En = pl.max_En;
 
     CholArgs ca;
+    memset(&ca, 0, sizeof(ca));
     ca.win = d_win;
     ca.ctl = d_ctl;
     ca.red = d_red;
@@ -469,6 +575,7 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
     ua.c = c;
 
     DecideArgs da;
+    memset(&da, 0, sizeof(da));
     da.win = d_win;
     da.ctl = d_ctl;
     da.opt_map = d_opt;
@@ -478,6 +585,7 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
     da.c = c;
 
     InitReduceArgs ia;
+    memset(&ia, 0, sizeof(ia));
     ia.win = d_win;
     ia.ctl = d_ctl;
     ia.partr = static_cast<const double *>(W_(pl.o_partr));
@@ -505,15 +613,40 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
         int steps_done = 0;
         int nsteps = iters;
         const int max_steps = iters * opt.max_trials;
+        // one LM step over every window: [linearise, reduce, factor + solve, update, decide]
+        auto step = [&](hipStream_t q) -> hipError_t {
+            hipError_t e;
+            if ((e = timed(ctx, LBA_KCLASS_LINEARIZE, q,
+                           [&] { return launch_linearize(la, ntiles, pl.lin_lds, false, pl.mixed, q); })) != hipSuccess)
+                return e;
+            if ((e = timed(ctx, LBA_KCLASS_REDUCE, q, [&] { return launch_reduce(ra, nw, q); })) != hipSuccess) return e;
+            if ((e = timed(ctx, LBA_KCLASS_CHOLESKY, q, [&] { return launch_cholesky(ca, nw, pl.chol_lds, q); })) !=
+                hipSuccess)
+                return e;
+            if ((e = timed(ctx, LBA_KCLASS_UPDATE, q,
+                           [&] { return launch_update(ua, ntiles, pl.upd_lds, pl.mixed, q); })) != hipSuccess)
+                return e;
+            return timed(ctx, LBA_KCLASS_DECIDE, q, [&] { return launch_decide(da, nw, q); });
+        };
+        hipGraphExec_t exec = nullptr;
+        if (opt.use_graphs && !ctx->prof && iters > 0) {
+            std::string key;
+            auto add = [&](const void *p, size_t n) { key.append(static_cast<const char *>(p), n); };
+            add(&la, sizeof(la));
+            add(&ra, sizeof(ra));
+            add(&ca, sizeof(ca));
+            add(&ua, sizeof(ua));
+            add(&da, sizeof(da));
+            const int64_t dims[6] = {ntiles, nw, (int64_t)pl.lin_lds, (int64_t)pl.chol_lds, (int64_t)pl.upd_lds,
+                                     pl.mixed ? 1 : 0};
+            add(dims, sizeof(dims));
+            st = step_graph(ctx, key, step, &exec);
+            if (st != LBA_OK) return st;
+        }
         while (nsteps > 0 && steps_done < max_steps) {
             for (int k = 0; k < nsteps; ++k) {
-                HIPCHK(timed(ctx, LBA_KCLASS_LINEARIZE, s,
-                             [&] { return launch_linearize(la, ntiles, pl.lin_lds, false, pl.mixed, s); }));
-                HIPCHK(timed(ctx, LBA_KCLASS_REDUCE, s, [&] { return launch_reduce(ra, nw, s); }));
-                HIPCHK(timed(ctx, LBA_KCLASS_CHOLESKY, s, [&] { return launch_cholesky(ca, nw, pl.chol_lds, s); }));
-                HIPCHK(timed(ctx, LBA_KCLASS_UPDATE, s,
-                             [&] { return launch_update(ua, ntiles, pl.upd_lds, pl.mixed, s); }));
-                HIPCHK(timed(ctx, LBA_KCLASS_DECIDE, s, [&] { return launch_decide(da, nw, s); }));
+                if (exec) HIPCHK(hipGraphLaunch(exec, s));
+                else HIPCHK(step(s));
             }
             steps_done += nsteps;
             HIPCHK(hipMemcpyAsync(down, d_ctl, sizeof(Ctl) * nw, hipMemcpyDeviceToHost, s));
@@ -535,6 +668,218 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
         HIPCHK(hipStreamSynchronize(s));
     }
     HIPCHK(collect_timing(ctx));
+    return LBA_OK;
+}
+
+
+// ------------------------------------------------------------------------------------
+// differentiation form
+// ------------------------------------------------------------------------------------
+struct CostPlan {
+    int nw = 0;
+    int maxK = 0;
+    std::vector<CostWin> win;
+    std::vector<Tile> tiles;
+    std::vector<int32_t> kf_off, pt_off, obs_off;
+    size_t o_win, o_tiles, o_kfoff, o_ptoff, o_obsoff, o_upload_end, o_ptstart, o_partF, o_partG, o_err, total;
+};
+
+lba_status build_cost_plan(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, CostPlan &cp) {
+    if (!P) return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "problem is NULL");
+    if (P->n_kf < 0 || P->n_pt < 0 || P->n_obs < 0)
+        return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "negative size");
+    if (P->n_levels < 1 || P->n_levels > kMaxLevels)
+        return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "n_levels must be in [1, %d]", kMaxLevels);
+    if (!P->sigma2) return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "sigma2 (host) is NULL");
+    for (int i = 0; i < P->n_levels; ++i)
+        if (!(P->sigma2[i] > 0.0) || !std::isfinite(P->sigma2[i]))
+            return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "sigma2[%d] must be positive", i);
+    if (P->n_kf > 0 && !P->T_cw) return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "T_cw is NULL");
+    if (P->n_obs > 0 && (!P->obs_kf || !P->obs_pt || !P->obs_type || !P->obs_oct))
+        return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "an observation array is NULL");
+    if (!(P->cam.fx > 0.0) || !(P->cam.fy > 0.0) || !std::isfinite(P->cam.cx) ||
+        !std::isfinite(P->cam.cy) || !std::isfinite(P->cam.bf))
+        return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "invalid intrinsics");
+    if (B) {
+        if (B->n_windows < 1 || !B->kf_off || !B->pt_off || !B->obs_off)
+            return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "invalid batch description");
+        cp.nw = B->n_windows;
+        cp.kf_off.assign(B->kf_off, B->kf_off + cp.nw + 1);
+        cp.pt_off.assign(B->pt_off, B->pt_off + cp.nw + 1);
+        cp.obs_off.assign(B->obs_off, B->obs_off + cp.nw + 1);
+    } else {
+        cp.nw = 1;
+        cp.kf_off = {0, P->n_kf};
+        cp.pt_off = {0, P->n_pt};
+        cp.obs_off = {0, P->n_obs};
+    }
+    const int nw = cp.nw;
+    if (cp.kf_off[0] != 0 || cp.pt_off[0] != 0 || cp.obs_off[0] != 0 || cp.kf_off[nw] != P->n_kf ||
+        cp.pt_off[nw] != P->n_pt || cp.obs_off[nw] != P->n_obs)
+        return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "batch offsets must start at 0 and end at the totals");
+    const int ppt = choose_points_per_tile(ctx->opt, P->n_pt);
+    int64_t g = 0;
+    cp.win.resize(nw);
+    cp.tiles.clear();
+    for (int w = 0; w < nw; ++w) {
+        CostWin &W = cp.win[w];
+        W.kf0 = cp.kf_off[w];
+        W.K = cp.kf_off[w + 1] - cp.kf_off[w];
+        W.pt0 = cp.pt_off[w];
+        W.M = cp.pt_off[w + 1] - cp.pt_off[w];
+        W.ob0 = cp.obs_off[w];
+        W.N = cp.obs_off[w + 1] - cp.obs_off[w];
+        if (W.K < 0 || W.M < 0 || W.N < 0)
+            return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "batch offsets decrease at window %d", w);
+        if (W.K > kMaxKf)
+            return set_error(ctx, LBA_ERR_UNSUPPORTED, "window %d has %d keyframes (at most %d)", w, W.K, kMaxKf);
+        if (W.N > 0 && (W.M == 0 || W.K == 0))
+            return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "window %d has observations but no points or keyframes", w);
+        W.tile0 = (int)cp.tiles.size();
+        W.ntiles = (W.M + ppt - 1) / ppt;
+        for (int t = 0; t < W.ntiles; ++t) {
+            Tile T;
+            T.win = w;
+            T.p0 = W.pt0 + t * ppt;
+            T.p1 = W.pt0 + std::min(W.M, (t + 1) * ppt);
+            T.pad = 0;
+            cp.tiles.push_back(T);
+        }
+        W.g_off = g;
+        g += (int64_t)W.ntiles * W.K * 6;
+        cp.maxK = std::max(cp.maxK, W.K);
+    }
+    size_t o = 0;
+    cp.o_win = o;    o = align256(o + sizeof(CostWin) * nw);
+    cp.o_tiles = o;  o = align256(o + sizeof(Tile) * std::max<size_t>(cp.tiles.size(), 1));
+    cp.o_kfoff = o;  o = align256(o + sizeof(int32_t) * (nw + 1));
+    cp.o_ptoff = o;  o = align256(o + sizeof(int32_t) * (nw + 1));
+    cp.o_obsoff = o; o = align256(o + sizeof(int32_t) * (nw + 1));
+    cp.o_upload_end = o;
+    cp.o_ptstart = o; o = align256(o + sizeof(int32_t) * ((size_t)P->n_pt + 1));
+    cp.o_partF = o;   o = align256(o + sizeof(double) * std::max<size_t>(cp.tiles.size(), 1));
+    cp.o_partG = o;   o = align256(o + sizeof(double) * std::max<int64_t>(g, 1));
+    cp.o_err = o;     o = align256(o + sizeof(int32_t) * 16);
+    cp.total = o;
+    return LBA_OK;
+}
+
+lba_status cost_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, bool bwd, const float *xi,
+                     const float *X, const float *z, const uint8_t *mask, const double *grad_cost, double *cost,
+                     float *g_xi, float *g_X, float *g_z, void *ws, size_t ws_bytes, void *stream_ptr) {
+    if (!ctx) return LBA_ERR_INVALID_ARGUMENT;
+    ctx->err.clear();
+    CostPlan cp;
+    lba_status st = build_cost_plan(ctx, P, B, cp);
+    if (st != LBA_OK) return st;
+    if (P->n_pt > 0 && !X) return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "X is NULL");
+    if (P->n_obs > 0 && !z) return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "z is NULL");
+    if (!bwd && !cost) return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "cost is NULL");
+    if (bwd) {
+        if (!grad_cost) return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "grad_cost is NULL");
+        if ((P->n_kf > 0 && !g_xi) || (P->n_pt > 0 && !g_X) || (P->n_obs > 0 && !g_z))
+            return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "a gradient output is NULL");
+    }
+    if (!ws || ws_bytes < cp.total)
+        return set_error(ctx, LBA_ERR_WORKSPACE_TOO_SMALL, "workspace of %zu bytes given, %zu needed", ws_bytes,
+                         cp.total);
+    if (((uintptr_t)ws) & 255) return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "workspace not 256-byte aligned");
+    if (cost_lds_bytes(cp.maxK, bwd) > (size_t)ctx->max_lds)
+        return set_error(ctx, LBA_ERR_UNSUPPORTED, "window of %d keyframes does not fit in LDS", cp.maxK);
+
+    DeviceGuard dg;
+    HIPCHK(dg.enter(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream_ptr);
+    unsigned char *wsb = static_cast<unsigned char *>(ws);
+    const int nw = cp.nw;
+
+    st = ensure_pinned(ctx, cp.o_upload_end + 256);
+    if (st != LBA_OK) return st;
+    unsigned char *up = static_cast<unsigned char *>(ctx->pinned);
+    unsigned char *down = up + cp.o_upload_end;
+    memcpy(up + cp.o_win, cp.win.data(), sizeof(CostWin) * nw);
+    if (!cp.tiles.empty()) memcpy(up + cp.o_tiles, cp.tiles.data(), sizeof(Tile) * cp.tiles.size());
+    memcpy(up + cp.o_kfoff, cp.kf_off.data(), sizeof(int32_t) * (nw + 1));
+    memcpy(up + cp.o_ptoff, cp.pt_off.data(), sizeof(int32_t) * (nw + 1));
+    memcpy(up + cp.o_obsoff, cp.obs_off.data(), sizeof(int32_t) * (nw + 1));
+    HIPCHK(hipMemcpyAsync(wsb, up, cp.o_upload_end, hipMemcpyHostToDevice, s));
+    st = record_upload(ctx, s);
+    if (st != LBA_OK) return st;
+
+    auto W_ = [&](size_t off) { return reinterpret_cast<void *>(wsb + off); };
+    int32_t *d_ptstart = static_cast<int32_t *>(W_(cp.o_ptstart));
+    int32_t *d_err = static_cast<int32_t *>(W_(cp.o_err));
+
+    ObsView ob;
+    ob.kf = P->obs_kf;
+    ob.pt = P->obs_pt;
+    ob.z = z;
+    ob.type = P->obs_type;
+    ob.oct = P->obs_oct;
+    ob.n_obs = P->n_obs;
+    ob.z_f32 = 1;
+
+    MiscArgs m;
+    memset(&m, 0, sizeof(m));
+    m.kf_off_dev = static_cast<const int32_t *>(W_(cp.o_kfoff));
+    m.pt_off_dev = static_cast<const int32_t *>(W_(cp.o_ptoff));
+    m.obs_off_dev = static_cast<const int32_t *>(W_(cp.o_obsoff));
+    m.T_in = P->T_cw;
+    m.pt_start = d_ptstart;
+    m.obs = ob;
+    m.err = d_err;
+    m.n_kf = P->n_kf;
+    m.n_pt = P->n_pt;
+    m.n_levels = P->n_levels;
+    m.c.cam = {P->cam.fx, P->cam.fy, P->cam.cx, P->cam.cy, P->cam.bf};
+    m.c.n_windows = nw;
+
+    HIPCHK(timed(ctx, LBA_KCLASS_SETUP, s, [&] { return launch_setup(m, nw, s); }));
+    if (ctx->opt.check_inputs) {
+        HIPCHK(timed(ctx, LBA_KCLASS_VALIDATE, s, [&] { return launch_validate(m, s); }));
+        HIPCHK(hipMemcpyAsync(down, d_err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        int32_t in_err;
+        memcpy(&in_err, down, sizeof(int32_t));
+        if (in_err)
+            return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "invalid input: %s", describe_input_error(in_err).c_str());
+    }
+
+    CostArgs ca;
+    memset(&ca, 0, sizeof(ca));
+    ca.win = static_cast<const CostWin *>(W_(cp.o_win));
+    ca.tiles = static_cast<const Tile *>(W_(cp.o_tiles));
+    ca.pt_start = d_ptstart;
+    ca.T = P->T_cw;
+    ca.xi = xi;
+    ca.X = X;
+    ca.z = z;
+    ca.obs_kf = P->obs_kf;
+    ca.obs_pt = P->obs_pt;
+    ca.obs_type = P->obs_type;
+    ca.obs_oct = P->obs_oct;
+    ca.mask = mask;
+    ca.grad_cost = grad_cost;
+    ca.g_xi = g_xi;
+    ca.g_X = g_X;
+    ca.g_z = g_z;
+    ca.cost = cost;
+    ca.partF = static_cast<double *>(W_(cp.o_partF));
+    ca.partG = static_cast<double *>(W_(cp.o_partG));
+    ca.err = d_err + 1;
+    ca.n_obs = P->n_obs;
+    ca.cam = m.c.cam;
+    ca.huber2[0] = ctx->opt.huber2_mono;
+    ca.huber2[1] = ctx->opt.huber2_stereo;
+    for (int i = 0; i < P->n_levels; ++i) ca.inv_sigma2[i] = 1.0 / P->sigma2[i];
+    const int ntiles = (int)cp.tiles.size();
+    const int cls = bwd ? LBA_KCLASS_COST_BACKWARD : LBA_KCLASS_COST_FORWARD;
+    HIPCHK(timed(ctx, cls, s, [&] { return launch_cost(ca, ntiles, cp.maxK, bwd, s); }));
+    HIPCHK(launch_cost_reduce(ca, nw, bwd, s));
+    if (ctx->prof) {
+        HIPCHK(hipStreamSynchronize(s));
+        HIPCHK(collect_timing(ctx));
+    }
     return LBA_OK;
 }
 
@@ -571,6 +916,7 @@ void lba_default_options(lba_options *o) {
     o->chi2_stereo = 7.815;
     o->tau = 1e-5;
     o->points_per_tile = 0;
+    o->use_graphs = 1;
 }
 
 lba_status lba_create(const lba_options *opt, int32_t device, lba_ctx **out) {
@@ -595,6 +941,13 @@ lba_status lba_create(const lba_options *opt, int32_t device, lba_ctx **out) {
 
 void lba_destroy(lba_ctx *ctx) {
     if (!ctx) return;
+    if (ctx->upload_pending) (void)hipEventSynchronize(ctx->upload_ev);
+    for (auto &g : ctx->graphs) {
+        (void)hipGraphExecDestroy(g.exec);
+        (void)hipGraphDestroy(g.graph);
+    }
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    if (ctx->upload_ev) (void)hipEventDestroy(ctx->upload_ev);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     delete ctx;
@@ -639,6 +992,126 @@ lba_status lba_workspace_size(lba_ctx *ctx, const lba_problem *problem, const lb
 lba_status lba_solve(lba_ctx *ctx, const lba_problem *problem, lba_result *result, void *workspace,
                      size_t workspace_bytes, void *stream) {
     return solve_impl(ctx, problem, nullptr, result, workspace, workspace_bytes, stream);
+}
+
+lba_status lba_cost_workspace_size(lba_ctx *ctx, const lba_problem *problem, const lba_batch *batch,
+                                   size_t *bytes) {
+    if (!ctx || !bytes) return LBA_ERR_INVALID_ARGUMENT;
+    ctx->err.clear();
+    CostPlan cp;
+    lba_status st = build_cost_plan(ctx, problem, batch, cp);
+    if (st != LBA_OK) return st;
+    *bytes = cp.total;
+    return LBA_OK;
+}
+
+lba_status lba_cost_forward(lba_ctx *ctx, const lba_problem *problem, const lba_batch *batch, const float *xi,
+                            const float *X, const float *z, const uint8_t *mask, double *cost, void *workspace,
+                            size_t workspace_bytes, void *stream) {
+    return cost_impl(ctx, problem, batch, false, xi, X, z, mask, nullptr, cost, nullptr, nullptr, nullptr,
+                     workspace, workspace_bytes, stream);
+}
+
+lba_status lba_cost_backward(lba_ctx *ctx, const lba_problem *problem, const lba_batch *batch, const float *xi,
+                             const float *X, const float *z, const uint8_t *mask, const double *grad_cost,
+                             float *g_xi, float *g_X, float *g_z, void *workspace, size_t workspace_bytes,
+                             void *stream) {
+    return cost_impl(ctx, problem, batch, true, xi, X, z, mask, grad_cost, nullptr, g_xi, g_X, g_z, workspace,
+                     workspace_bytes, stream);
+}
+
+lba_status lba_tune(lba_ctx *ctx, const lba_problem *problem, const lba_batch *batch, void *stream,
+                    int32_t *points_per_tile) {
+    if (!ctx) return LBA_ERR_INVALID_ARGUMENT;
+    ctx->err.clear();
+    Plan pl0;
+    lba_status st = build_plan(ctx, problem, batch, pl0);
+    if (st != LBA_OK) return st;
+    bool present[3] = {false, false, false};
+    for (const WinInfo &W : pl0.win) present[kopt_class(W.Kopt)] = true;
+    // the smallest tiles give the most tiles, hence the largest workspace of any candidate
+    static const int cand[] = {64, 128, 256, 512, 1024, 2048, 4096};
+    const int smallest[3] = {cand[0], cand[0], cand[0]};
+    ctx->ppt_override = smallest;
+    Plan pmax;
+    st = build_plan(ctx, problem, batch, pmax);
+    ctx->ppt_override = nullptr;
+    if (st != LBA_OK) return st;
+
+    DeviceGuard dg;
+    HIPCHK(dg.enter(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    void *ws = nullptr, *T = nullptr, *X = nullptr, *fl = nullptr;
+    auto release = [&] {
+        (void)hipStreamSynchronize(s);
+        for (auto &g : ctx->graphs) {
+            (void)hipGraphExecDestroy(g.exec);
+            (void)hipGraphDestroy(g.graph);
+        }
+        ctx->graphs.clear();
+        if (ws) (void)hipFree(ws);
+        if (T) (void)hipFree(T);
+        if (X) (void)hipFree(X);
+        if (fl) (void)hipFree(fl);
+    };
+    if (hipMalloc(&ws, pmax.total) != hipSuccess ||
+        hipMalloc(&T, sizeof(double) * 12 * std::max(problem->n_kf, 1)) != hipSuccess ||
+        hipMalloc(&X, sizeof(double) * 3 * std::max(problem->n_pt, 1)) != hipSuccess ||
+        hipMalloc(&fl, std::max(problem->n_obs, 1)) != hipSuccess) {
+        release();
+        return set_error(ctx, LBA_ERR_HIP, "lba_tune: device allocation of %zu bytes failed", pmax.total);
+    }
+    const lba_options saved = ctx->opt;
+    const bool saved_prof = ctx->prof;
+    ctx->opt.iters_round1 = 3;
+    ctx->opt.iters_round2 = 0;
+    ctx->opt.points_per_tile = 0;
+    ctx->prof = false;
+    lba_result R = {static_cast<double *>(T), static_cast<double *>(X), static_cast<uint8_t *>(fl), nullptr};
+    int cfg[3];
+    double best = 0.0;
+    // time of one short solve (three LM steps on every window) with the tile table cfg;
+    // the first run captures the step graph, the second is timed
+    auto measure = [&](const int *c, double *sec) -> lba_status {
+        ctx->ppt_override = c;
+        for (int rep = 0; rep < 2; ++rep) {
+            if (hipStreamSynchronize(s) != hipSuccess) return set_error(ctx, LBA_ERR_HIP, "stream sync failed");
+            const auto t0 = std::chrono::steady_clock::now();
+            lba_status e = solve_impl(ctx, problem, batch, &R, ws, pmax.total, stream);
+            if (e != LBA_OK) return e;
+            *sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        }
+        return LBA_OK;
+    };
+    const int start = choose_points_per_tile(saved, problem->n_pt);
+    for (int c = 0; c < 3; ++c) cfg[c] = start;
+    st = measure(cfg, &best);
+    // coordinate descent over the classes present; a change must gain 2%
+    for (int c = 0; c < 3 && st == LBA_OK; ++c) {
+        if (!present[c]) continue;
+        for (int v : cand) {
+            if (v == cfg[c]) continue;
+            int trial[3] = {cfg[0], cfg[1], cfg[2]};
+            trial[c] = v;
+            double t = 0.0;
+            st = measure(trial, &t);
+            if (st != LBA_OK) break;
+            if (t < 0.98 * best) {
+                best = t;
+                cfg[c] = v;
+            }
+        }
+    }
+    ctx->ppt_override = nullptr;
+    ctx->opt = saved;
+    ctx->prof = saved_prof;
+    release();
+    if (st != LBA_OK) return st;
+    tune_signature(problem, pl0.nw, pl0.mixed, ctx->tuned_sig);
+    for (int c = 0; c < 3; ++c) ctx->tuned_ppt[c] = cfg[c];
+    if (points_per_tile)
+        for (int c = 0; c < 3; ++c) points_per_tile[c] = cfg[c];
+    return LBA_OK;
 }
 
 lba_status lba_solve_batch(lba_ctx *ctx, const lba_problem *problem, const lba_batch *batch, lba_result *result,

@@ -166,6 +166,36 @@ struct MiscArgs {
     SolveConsts c;
 };
 
+// differentiation form: one window of the robust-cost layer
+struct CostWin {
+    int32_t kf0, K, pt0, M, ob0, N;   // ranges in the concatenated arrays
+    int32_t tile0, ntiles;            // tiles of this window in the tile list
+    int64_t g_off;                    // doubles: per-tile pose-gradient partials (ntiles x K x 6)
+};
+
+struct CostArgs {
+    const CostWin *win;
+    const Tile *tiles;
+    const int32_t *pt_start;     // global point -> first global observation (n_pt + 1)
+    const double *T;             // base poses, n_kf x 12
+    const float *xi;             // left perturbations, n_kf x 6, or nullptr (zero)
+    const float *X;              // points, n_pt x 3
+    const float *z;              // measurements, 3 x n_obs planar
+    const int32_t *obs_kf, *obs_pt;
+    const uint8_t *obs_type, *obs_oct;
+    const uint8_t *mask;         // 1 = observation left out, or nullptr
+    const double *grad_cost;     // backward: dL/dcost per window
+    float *g_xi, *g_X, *g_z;     // backward outputs
+    double *cost;                // forward output, per window
+    double *partF;               // per tile cost
+    double *partG;               // per tile pose-gradient partials (left-trivialised)
+    int32_t *err;                // set when a tile meets an observation it cannot place
+    int32_t n_obs;
+    CamParams cam;
+    double huber2[2];
+    double inv_sigma2[kMaxLevels];
+};
+
 // ------------------------------------------------------------------------------------
 // launchers (one per translation unit that owns the kernel)
 // ------------------------------------------------------------------------------------
@@ -180,11 +210,14 @@ hipError_t launch_setup(const MiscArgs &a, int n_windows, hipStream_t s);
 hipError_t launch_validate(const MiscArgs &a, hipStream_t s);
 hipError_t launch_flags(const MiscArgs &a, hipStream_t s);
 hipError_t launch_finalize(const MiscArgs &a, int n_windows, hipStream_t s);
+hipError_t launch_cost(const CostArgs &a, int ntiles, int max_k, bool backward, hipStream_t s);
+hipError_t launch_cost_reduce(const CostArgs &a, int n_windows, bool backward, hipStream_t s);
 
 // LDS bytes of the linearisation / update blocks for a window shape
 size_t lin_lds_bytes(int K, int n, int waves, bool mixed);
 size_t upd_lds_bytes(int K, int n, int waves, bool mixed);
 size_t chol_lds_bytes(int n);
+size_t cost_lds_bytes(int K, bool backward);
 
 #if defined(__HIPCC__)
 // ------------------------------------------------------------------------------------

@@ -27,10 +27,12 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "out of memory", -3: "HIP runtime
 # every symbol include/lba.h declares
 EXPORTS = ["lba_abi_version", "lba_status_string", "lba_default_options", "lba_create",
            "lba_destroy", "lba_last_error", "lba_set_options", "lba_workspace_size", "lba_solve",
-           "lba_solve_batch", "lba_profile_enable", "lba_profile_read"]
+           "lba_solve_batch", "lba_profile_enable", "lba_profile_read", "lba_cost_workspace_size",
+           "lba_cost_forward", "lba_cost_backward", "lba_tune"]
 
 KERNEL_CLASSES = ["linearize", "linearize_init", "reduce", "cholesky", "update", "decide",
-                  "init_reduce", "setup", "validate", "flags", "finalize"]
+                  "init_reduce", "setup", "validate", "flags", "finalize", "cost_forward",
+                  "cost_backward"]
 
 
 class Options(C.Structure):
@@ -38,7 +40,7 @@ class Options(C.Structure):
                 ("max_trials", C.c_int32), ("round2_robust", C.c_int32), ("check_inputs", C.c_int32),
                 ("huber2_mono", C.c_double), ("huber2_stereo", C.c_double),
                 ("chi2_mono", C.c_double), ("chi2_stereo", C.c_double), ("tau", C.c_double),
-                ("points_per_tile", C.c_int32), ("reserved", C.c_int32)]
+                ("points_per_tile", C.c_int32), ("use_graphs", C.c_int32)]
 
 
 class Intrinsics(C.Structure):
@@ -100,6 +102,20 @@ def library():
         L.lba_profile_read.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int64),
                                        C.POINTER(C.c_double)]
         L.lba_profile_read.restype = C.c_int
+        L.lba_cost_workspace_size.argtypes = [C.c_void_p, C.POINTER(Problem), C.POINTER(Batch),
+                                              C.POINTER(C.c_size_t)]
+        L.lba_cost_workspace_size.restype = C.c_int
+        L.lba_cost_forward.argtypes = [C.c_void_p, C.POINTER(Problem), C.POINTER(Batch), C.c_void_p,
+                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                       C.c_size_t, C.c_void_p]
+        L.lba_cost_forward.restype = C.c_int
+        L.lba_cost_backward.argtypes = [C.c_void_p, C.POINTER(Problem), C.POINTER(Batch), C.c_void_p,
+                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
+        L.lba_cost_backward.restype = C.c_int
+        L.lba_tune.argtypes = [C.c_void_p, C.POINTER(Problem), C.POINTER(Batch), C.c_void_p,
+                               C.POINTER(C.c_int32)]
+        L.lba_tune.restype = C.c_int
         _lib = L
     return _lib
 
@@ -154,6 +170,16 @@ class Context:
                         "lba_profile_read")
             out[name] = (n.value, ms.value)
         return out
+
+    def tune(self, prob: "DeviceProblem", stream=None) -> list:
+        """Run the tile tuner on this problem (see lba_tune); returns the points-per-tile
+        table by optimisable-keyframe class (<= 10, <= 20, > 20)."""
+        import torch
+        stream = stream or torch.cuda.current_stream(prob.device)
+        out = (C.c_int32 * 3)()
+        self._check(self.lib.lba_tune(self.handle, C.byref(prob.problem), C.byref(prob.batch),
+                                      C.c_void_p(stream.cuda_stream), out), "lba_tune")
+        return list(out)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -259,3 +285,117 @@ def solve(data: dict, device="cuda", z_f32: bool = False, **options) -> dict:
                outlier=s.outlier.cpu().numpy().astype(bool), stats=s.stats_dicts())
     ctx.close()
     return out
+
+
+# ----------------------------------------------------------------------------------------
+# differentiation form
+# ----------------------------------------------------------------------------------------
+class CostLayer:
+    """The robust reprojection cost of every window of a batch as a differentiable
+    function of FP32 pose perturbations xi (n_kf, 6), points X (n_pt, 3) and
+    measurements z (3, n_obs); the topology, base poses, octaves and intrinsics come from
+    ``data`` (one window dict or a concatenation, as for ``DeviceProblem``).
+
+    ``forward`` and ``backward`` call lba_cost_forward / lba_cost_backward; use
+    ``robust_cost`` for the autograd form."""
+
+    def __init__(self, ctx: Context, data: dict, device="cuda"):
+        import torch
+        self.ctx = ctx
+        self.prob = DeviceProblem(data, device=device, z_f32=True)
+        self.torch = torch
+        p = self.prob
+        ws = C.c_size_t(0)
+        ctx._check(ctx.lib.lba_cost_workspace_size(ctx.handle, C.byref(p.problem), C.byref(p.batch), C.byref(ws)),
+                   "lba_cost_workspace_size")
+        self.ws_bytes = ws.value
+        self.ws = torch.empty(max(self.ws_bytes, 256) + 256, dtype=torch.uint8, device=p.device)
+        self.ws_ptr = (self.ws.data_ptr() + 255) // 256 * 256
+        self.n_kf, self.n_pt, self.n_obs = p.T_cw.shape[0], p.X.shape[0], p.obs_kf.shape[0]
+        self.n_windows = p.n_windows
+
+    def _args(self, xi, X, z, mask):
+        t = self.torch
+        dev = self.prob.device
+
+        def chk(x, shape, dtype, name):
+            if x is None:
+                return None
+            if x.device != dev or x.dtype != dtype or tuple(x.shape) != shape or not x.is_contiguous():
+                raise ValueError(f"{name}: expected contiguous {dtype} {shape} on {dev}, got "
+                                 f"{x.dtype} {tuple(x.shape)} on {x.device}")
+            return x
+        xi = chk(xi, (self.n_kf, 6), t.float32, "xi")
+        X = chk(X, (self.n_pt, 3), t.float32, "X")
+        z = chk(z, (3, self.n_obs), t.float32, "z")
+        mask = chk(mask, (self.n_obs,), t.uint8, "mask")
+        ptr = lambda x: None if x is None else x.data_ptr()
+        return xi, X, z, mask, ptr
+
+    def forward(self, xi, X, z, mask=None, stream=None):
+        """Cost per window (float64, (n_windows,))."""
+        t = self.torch
+        xi, X, z, mask, ptr = self._args(xi, X, z, mask)
+        cost = t.empty(self.n_windows, dtype=t.float64, device=self.prob.device)
+        stream = stream or t.cuda.current_stream(self.prob.device)
+        st = self.ctx.lib.lba_cost_forward(self.ctx.handle, C.byref(self.prob.problem), C.byref(self.prob.batch),
+                                           ptr(xi), ptr(X), ptr(z), ptr(mask), cost.data_ptr(),
+                                           C.c_void_p(self.ws_ptr), C.c_size_t(self.ws_bytes),
+                                           C.c_void_p(stream.cuda_stream))
+        self.ctx._check(st, "lba_cost_forward")
+        return cost
+
+    def backward(self, xi, X, z, grad_cost, mask=None, stream=None):
+        """Gradients (g_xi (n_kf, 6), g_X (n_pt, 3), g_z (3, n_obs)), all float32."""
+        t = self.torch
+        xi, X, z, mask, ptr = self._args(xi, X, z, mask)
+        gc = grad_cost.to(device=self.prob.device, dtype=t.float64).contiguous()
+        if tuple(gc.shape) != (self.n_windows,):
+            raise ValueError(f"grad_cost: expected ({self.n_windows},), got {tuple(gc.shape)}")
+        g_xi = t.empty((self.n_kf, 6), dtype=t.float32, device=self.prob.device)
+        g_X = t.empty((self.n_pt, 3), dtype=t.float32, device=self.prob.device)
+        g_z = t.empty((3, self.n_obs), dtype=t.float32, device=self.prob.device)
+        stream = stream or t.cuda.current_stream(self.prob.device)
+        st = self.ctx.lib.lba_cost_backward(self.ctx.handle, C.byref(self.prob.problem), C.byref(self.prob.batch),
+                                            ptr(xi), ptr(X), ptr(z), ptr(mask), gc.data_ptr(), g_xi.data_ptr(),
+                                            g_X.data_ptr(), g_z.data_ptr(), C.c_void_p(self.ws_ptr),
+                                            C.c_size_t(self.ws_bytes), C.c_void_p(stream.cuda_stream))
+        self.ctx._check(st, "lba_cost_backward")
+        return g_xi, g_X, g_z
+
+
+def _autograd_function():
+    import torch
+
+    class RobustReprojCost(torch.autograd.Function):
+        """cost = RobustReprojCost.apply(layer, xi, X, z, mask): the robust reprojection
+        cost per window; the backward pass is lba_cost_backward (Jacobians recomputed)."""
+
+        @staticmethod
+        def forward(fctx, layer, xi, X, z, mask):
+            fctx.layer = layer
+            fctx.mask = mask
+            fctx.save_for_backward(xi, X, z)
+            d = lambda x: None if x is None else x.detach()
+            return layer.forward(d(xi), X.detach(), z.detach(), mask)
+
+        @staticmethod
+        def backward(fctx, grad_cost):
+            xi, X, z = fctx.saved_tensors
+            d = lambda x: None if x is None else x.detach()
+            g_xi, g_X, g_z = fctx.layer.backward(d(xi), X.detach(), z.detach(), grad_cost, fctx.mask)
+            return (None, g_xi if fctx.needs_input_grad[1] else None, g_X if fctx.needs_input_grad[2] else None,
+                    g_z if fctx.needs_input_grad[3] else None, None)
+
+    return RobustReprojCost
+
+
+_RRC = None
+
+
+def robust_cost(layer: CostLayer, xi, X, z, mask=None):
+    """Differentiable cost per window (see CostLayer)."""
+    global _RRC
+    if _RRC is None:
+        _RRC = _autograd_function()
+    return _RRC.apply(layer, xi, X, z, mask)
