@@ -19,9 +19,9 @@
 // chunks of whole points with at most 256 observations (one per thread):
 //   - the point gradient is the sum over the point's (contiguous) observations, formed by
 //     one thread per point from per-observation terms staged in LDS;
-//   - the pose terms are summed per keyframe inside each wavefront (a ballot picks one
-//     keyframe at a time and the lanes holding it reduce), into per-wavefront LDS rows
-//     that the block adds in a fixed order at the end of the tile.
+//   - the pose terms are added per keyframe into per-wavefront LDS rows (LDS atomics
+//     within one wavefront only), which the block adds in a fixed order at the end of
+//     the tile.
 #include "lba_internal.h"
 
 namespace lba {
@@ -163,18 +163,13 @@ __global__ __launch_bounds__(kCostThreads) void k_cost(CostArgs a) {
             }
         }
         if (BWD) {
-            // pose terms: one keyframe of the wavefront at a time
-            unsigned long long pend = __ballot(valid);
-            while (pend) {
-                const int leader = __ffsll((unsigned long long)pend) - 1;
-                const int c = __shfl(kl, leader, 64);
-                const bool mine = valid && kl == c;
-                pend &= ~__ballot(mine);
+            // pose terms into this wavefront's own rows: lanes of one wavefront that hit the
+            // same keyframe are serialised by the LDS unit in a fixed order, and no other
+            // wavefront touches these rows, so the sums are the same on every run
+            if (valid) {
+                double *row = gc + (wave * K + kl) * 6;
 #pragma unroll
-                for (int qd = 0; qd < 6; ++qd) {
-                    const double v = wave_sum(mine ? (double)gd[qd] : 0.0);
-                    if (lane == 0) gc[(wave * K + c) * 6 + qd] += v;
-                }
+                for (int qd = 0; qd < 6; ++qd) lds_add(row + qd, (double)gd[qd]);
             }
             __syncthreads();
             // point gradients: one thread per point of the chunk (points without

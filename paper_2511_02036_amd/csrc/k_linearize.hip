@@ -4,25 +4,28 @@
 // of the reduced camera system
 //     S = Hpp + lambda I - sum_j sum_{a,b in obs(j)} W_a V_j^-1 W_b^T,
 //     r = bp - sum_j sum_{a in obs(j)} W_a V_j^-1 bl_j,
-// lives in registers for the whole tile: the 6 x 6 block of every pair of optimisable
-// keyframes is split into six rows, and each thread owns up to six such rows (their
-// partial sums stay in FP64 registers, so no two threads ever add into the same entry
-// and no atomics touch S).  The tile is walked in chunks of whole points holding at most
-// CO observations (CO = 512 for FP32 arithmetic, 256 for FP64); per chunk:
-//   1. one thread per observation forms the residual (FP64), the robust weight, the
-//      Gauss-Newton blocks Hll_a, W_a, Hpp_a in factored form (Real) and the gradient
-//      pieces bl_a, bp_a (FP64);
-//   2. the threads of each point sum Hll (Real) and bl (FP64) through LDS, factor
+// lives in registers for the whole tile: 14 groups of 36 threads each own one entry of
+// the 6 x 6 blocks of every 14th pair of optimisable keyframes (FP64 partial sums, so no
+// two threads ever add into the same entry and no atomics touch S or r; the unused upper
+// triangle of a diagonal block carries that camera's six entries of r).  The tile is
+// walked in chunks of whole points holding at most CO observations (CO = 256 for FP32
+// arithmetic, 128 for FP64); per chunk:
+//   1. one thread per observation forms the residual (FP64), the robust weight and the
+//      FP64 point block Hll_a and gradient bl_a;
+//   2. the threads of each point sum Hll and bl through LDS, factor
 //      V = Hll + lambda I = L L^T, and stage Z_a = W_a L^-T, D_a = Hpp_a - Z_a Z_a^T and
 //      r_a = bp_a - Z_a L^-1 bl (so W_a V^-1 W_b^T = Z_a Z_b^T) in LDS;
 //   3. every pair (a, b), a <= b, of optimisable observations of one point is counted
 //      and then placed, by camera block, into a block-sorted pair list (LDS integer
 //      atomics give each pair its slot in its block's list);
-//   4. every owner walks the pair lists of its block rows and accumulates -Z_a Z_b^T
-//      (or D_a for a pair of an observation with itself); the owners of r walk the
-//      diagonal-block lists.
-// At the end of the tile each owner writes its rows to the tile's partial system; a
+//   4. in batches of PB pairs, one thread per pair writes the pair's signed 6 x 6
+//      contribution (-Z_a Z_b^T, or D_a and r_a for a pair of an observation with
+//      itself) to LDS in list order; every owner then adds up its entry over the
+//      contiguous run of its block.
+// At the end of the tile each owner writes its entry to the tile's partial system; a
 // separate kernel sums the partials of a window in a fixed order (no global atomics).
+// The order inside a block's run comes from the atomics, so the FP64 sums may differ
+// between runs in their last bits.
 // The gradient bp itself is not needed: the gain-ratio denominator uses
 // dp^T bp = dp^T r + sum_j q_j^T V_j^-1 bl_j (q_j = sum_a W_a^T dp), whose point part
 // the update kernel forms.
@@ -34,14 +37,18 @@
 namespace lba {
 
 constexpr int kNT = kLinThreads;           // 512
-constexpr int kSlots = 6;                  // block rows per thread (6 * 512 >= 6 * 465)
+constexpr int kGroups = kLinThreads / 36;  // 14 groups of 36 threads, one block entry each
+constexpr int kSlots = 34;                 // blocks per group (14 * 34 >= 465)
 constexpr int kMaxBlocks = 465;            // Kopt <= 30
 constexpr int kMaxN = 180;
 
 template <typename Real>
 struct LinCfg {
-    static constexpr int CO = sizeof(Real) == 4 ? 512 : 256;          // observations per chunk
-    static constexpr int PCAP = sizeof(Real) == 4 ? 4096 : 2080;      // pairs per chunk (>= 64*65/2)
+    static constexpr int CO = sizeof(Real) == 4 ? 256 : 128;   // observations per chunk
+    static constexpr int PCAP = 2080;                          // pairs per chunk (>= 64*65/2)
+    static constexpr int PB = sizeof(Real) == 4 ? 512 : 256;   // pair products per batch
+    static constexpr int PS = 37;                              // product row stride (odd)
+    static constexpr int RPT = 6 * PB / kNT;                   // product rows per thread
 };
 
 template <typename Real>
@@ -51,15 +58,84 @@ struct LinSmem {
     Real *Z;         // CO x 18
     Real *D;         // CO x 21   lower triangle of Hpp_a - Z_a Z_a^T (phase 1: FP64 Hll_a, 6 each)
     double *rd;      // CO x 6    (phase 1: bl_a in the first 3) r_a
-    double *hd;      // kMaxN: INIT only, diagonal of Hpp
+    double *hd;      // kMaxN: r (INIT: diagonal of Hpp of the chunk)
     unsigned *pairs; // PCAP
+    Real *prod;      // PB x PS: signed 6 x 6 contribution of each pair of the current batch
     int *cnt;        // kMaxBlocks + 1 (then list offsets)
     int *cur;        // kMaxBlocks
     int *oka;        // CO: optimisable camera of the chunk observation (-1: none)
     int *oseg;       // CO: s0 | s1 << 16 (chunk-local observation range of its point)
     int *scan;       // 16: per-wavefront totals
+    unsigned long long *touch;   // 2 x kGroups: per group, blocks with pairs in the batch
     double *red;     // 16 x 2
 };
+
+// A pair of an observation with itself contributes D_a to the lower triangle of its
+// diagonal block and r_a to r.  r_a (six doubles) is parked in the unused upper triangle
+// of that pair's product: as 32-bit halves at the float positions
+// 1 2 | 3 4 | 5 8 | 9 10 | 11 15 | 16 17 (5 bits each below), or as whole doubles at the
+// positions 1 2 3 4 5 8 (4 bits each).
+constexpr unsigned long long kRPosF = 0x8c1eb5250520c41ull;
+constexpr unsigned kRPosD = 0x854321u;
+
+__device__ __forceinline__ void put_r(float *row, int i, double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    row[(kRPosF >> (10 * i)) & 31] = __uint_as_float((unsigned)b);
+    row[(kRPosF >> (10 * i + 5)) & 31] = __uint_as_float((unsigned)(b >> 32));
+}
+__device__ __forceinline__ void put_r(double *row, int i, double v) { row[(kRPosD >> (4 * i)) & 15] = v; }
+__device__ __forceinline__ double get_r(const float *row, int i) {
+    const unsigned long long lo = __float_as_uint(row[(kRPosF >> (10 * i)) & 31]);
+    const unsigned long long hi = __float_as_uint(row[(kRPosF >> (10 * i + 5)) & 31]);
+    return __longlong_as_double((long long)(lo | (hi << 32)));
+}
+__device__ __forceinline__ double get_r(const double *row, int i) { return row[(kRPosD >> (4 * i)) & 15]; }
+
+// rows R0 .. R0 + NR - 1 of the signed 6 x 6 product of one pair (la, lb, flag fl)
+template <int R0, int NR, typename Real>
+__device__ __forceinline__ void pair_product(const LinSmem<Real> &sm, int la, int lb, int fl, Real *out) {
+    if (fl == 1) {   // D_a (lower triangle) and r_a
+#pragma unroll
+        for (int i = R0; i < R0 + NR; ++i)
+#pragma unroll
+            for (int j = 0; j <= i; ++j) out[i * 6 + j] = sm.D[la * 21 + i * (i + 1) / 2 + j];
+        if (R0 == 0)
+#pragma unroll
+            for (int i = 0; i < 6; ++i) put_r(out, i, sm.rd[la * 6 + i]);
+        return;
+    }
+    // rows i of Z_a (and Z_b) stay in registers; rows j are streamed from LDS
+    const Real *za = sm.Z + la * 18, *zb = sm.Z + lb * 18;
+    Real ai[3 * NR], bi[3 * NR];
+#pragma unroll
+    for (int c = 0; c < 3 * NR; ++c) {
+        ai[c] = za[R0 * 3 + c];
+        bi[c] = fl == 2 ? zb[R0 * 3 + c] : (Real)0;
+    }
+    if (fl == 0) {   // -Z_a Z_b^T, camera of a before camera of b
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            const Real b0 = zb[j * 3], b1 = zb[j * 3 + 1], b2 = zb[j * 3 + 2];
+#pragma unroll
+            for (int i = 0; i < NR; ++i)
+                out[(R0 + i) * 6 + j] = -(ai[i * 3] * b0 + ai[i * 3 + 1] * b1 + ai[i * 3 + 2] * b2);
+        }
+    } else {         // one camera twice: -(Z_a Z_b^T + Z_b Z_a^T), lower triangle
+#pragma unroll
+        for (int j = 0; j < R0 + NR; ++j) {
+            const Real b0 = zb[j * 3], b1 = zb[j * 3 + 1], b2 = zb[j * 3 + 2];
+            const Real a0 = za[j * 3], a1 = za[j * 3 + 1], a2 = za[j * 3 + 2];
+#pragma unroll
+            for (int i = 0; i < NR; ++i)
+                if (j <= R0 + i)
+                    out[(R0 + i) * 6 + j] = -(ai[i * 3] * b0 + ai[i * 3 + 1] * b1 + ai[i * 3 + 2] * b2 +
+                                              bi[i * 3] * a0 + bi[i * 3 + 1] * a1 + bi[i * 3 + 2] * a2);
+        }
+        if (R0 == 0)
+#pragma unroll
+            for (int i = 0; i < 6; ++i) put_r(out, i, 0.0);
+    }
+}
 
 static __host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -74,8 +150,10 @@ __host__ __device__ inline size_t lin_carve(unsigned char *base, int K, LinSmem<
     void *D = take(sizeof(Real) * C::CO * 21);
     void *rd = take(sizeof(double) * C::CO * 6);
     void *pairs = take(sizeof(unsigned) * C::PCAP);
+    void *prod = take(sizeof(Real) * C::PB * C::PS);
     void *cnt = take(sizeof(int) * (kMaxBlocks + 1));
     void *cur = take(sizeof(int) * kMaxBlocks);
+    void *touch = take(sizeof(unsigned long long) * 2 * kGroups);
     void *oka = take(sizeof(int) * C::CO);
     void *oseg = take(sizeof(int) * C::CO);
     void *scan = take(sizeof(int) * 16);
@@ -83,7 +161,7 @@ __host__ __device__ inline size_t lin_carve(unsigned char *base, int K, LinSmem<
     void *hd = take(sizeof(double) * kMaxN);
     if (s) {
         s->T = (double *)T; s->opt = (int *)opt; s->Z = (Real *)Z; s->D = (Real *)D; s->rd = (double *)rd;
-        s->pairs = (unsigned *)pairs; s->cnt = (int *)cnt; s->cur = (int *)cur; s->oka = (int *)oka;
+        s->pairs = (unsigned *)pairs; s->prod = (Real *)prod; s->cnt = (int *)cnt; s->cur = (int *)cur; s->touch = (unsigned long long *)touch; s->oka = (int *)oka;
         s->oseg = (int *)oseg; s->scan = (int *)scan; s->red = (double *)red; s->hd = (double *)hd;
     }
     return o;
@@ -97,6 +175,17 @@ size_t lin_lds_bytes(int K, int n, int waves, bool mixed) {
 
 // index of block (ka <= kb) of the upper block triangle, row-major
 __device__ __forceinline__ int block_id(int ka, int kb, int Kopt) { return ka * Kopt - ka * (ka - 1) / 2 + (kb - ka); }
+
+// block row ka of block index B (0 <= B < Kopt (Kopt + 1) / 2): the largest ka with
+// block_id(ka, ka) <= B, from the quadratic's root and one correction step each way
+__device__ __forceinline__ int block_row(int B, int Kopt) {
+    const float c = 2.0f * Kopt + 1.0f;
+    int ka = (int)((c - sqrtf(fmaxf(c * c - 8.0f * B, 0.0f))) * 0.5f);
+    ka = min(max(ka, 0), max(Kopt - 1, 0));
+    if (ka > 0 && block_id(ka, ka, Kopt) > B) --ka;
+    if (ka + 1 < Kopt && block_id(ka + 1, ka + 1, Kopt) <= B) ++ka;
+    return ka;
+}
 
 // inclusive scan of one int per thread over the block (512 threads)
 __device__ __forceinline__ int block_inclusive_scan(int v, int *scan, int tid) {
@@ -134,14 +223,27 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
     for (int i = tid; i < 12 * K; i += kNT) sm.T[i] = a.T[(int64_t)W.kf0 * 12 + i];
     for (int i = tid; i < K; i += kNT) sm.opt[i] = a.opt_map[W.kf0 + i];
 
-    // ---- owned block rows: slot s = tid + k * kNT -> block s / 6 (kA <= kB), row s % 6 ----
-    const int nslot = INIT ? 0 : 6 * nblk;
-    double acc[kSlots][6];
+    // ---- owned entries: thread g * 36 + q (g < 14) owns entry q = 6 i + j of the 6 x 6
+    // blocks B = g + 14 k (kA <= kB).  In a diagonal block the entries j <= i are S, the six
+    // upper positions 1 2 3 4 5 8 accumulate r of that camera, the rest are unused.
+    const int grp = tid / 36, qe = tid - 36 * grp;
+    const int nent = INIT ? 0 : nblk;
+    double acc[kSlots];
 #pragma unroll
-    for (int k = 0; k < kSlots; ++k)
-#pragma unroll
-        for (int j = 0; j < 6; ++j) acc[k][j] = 0.0;
-    double racc = 0.0;   // r[tid] (INIT: Hpp diagonal entry tid)
+    for (int k = 0; k < kSlots; ++k) acc[k] = 0.0;
+    unsigned long long m_r = 0, m_skip = 0;   // per slot: accumulates r / owns nothing
+    {
+        const int ie = qe / 6, je = qe - 6 * (qe / 6);
+        const bool rpos = qe == 8 || (qe >= 1 && qe <= 5);
+        for (int k = 0; k < kSlots; ++k) {
+            const int B = grp + kGroups * k;
+            const int kA = block_row(B, Kopt);
+            const bool diag = B == block_id(kA, kA, Kopt);
+            if (grp >= kGroups || B >= nent || (diag && je > ie && !rpos)) m_skip |= 1ull << k;
+            else if (diag && rpos) m_r |= 1ull << k;
+        }
+    }
+    double racc = 0.0;   // INIT: Hpp diagonal entry tid
     __syncthreads();
 
     const CamParams cam = a.c.cam;
@@ -307,6 +409,7 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             sm.cnt[B] = 0;
             sm.cur[B] = 0;
         }
+        if (tid < 2 * kGroups) sm.touch[tid] = 0ull;
         __syncthreads();
 
         // ---- 3. pair lists sorted by camera block --------------------------------------
@@ -340,48 +443,50 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
         }
         __syncthreads();
 
-        // ---- 4. owners accumulate their block rows and r -------------------------------
-#pragma unroll
-        for (int k = 0; k < kSlots; ++k) {
-            const int s_ = tid + k * kNT;
-            if (s_ >= nslot) continue;
-            const int B = s_ / 6, i = s_ - 6 * B;
-            const int p0 = sm.cnt[B], p1 = sm.cnt[B + 1];
-            for (int pi = p0; pi < p1; ++pi) {
-                const unsigned e = sm.pairs[pi];
-                const int la = e & 1023, lb = (e >> 10) & 1023, fl = e >> 20;
-                if (fl == 1) {
-                    const Real *d = sm.D + la * 21 + i * (i + 1) / 2;
-#pragma unroll
-                    for (int j = 0; j < 6; ++j)
-                        if (j <= i) acc[k][j] += (double)d[j];
-                } else {
-                    const Real *za = sm.Z + la * 18, *zb = sm.Z + lb * 18;
-                    const Real a0 = za[i * 3], a1 = za[i * 3 + 1], a2 = za[i * 3 + 2];
-                    if (fl == 0) {
-#pragma unroll
-                        for (int j = 0; j < 6; ++j)
-                            acc[k][j] -= (double)(a0 * zb[j * 3] + a1 * zb[j * 3 + 1] + a2 * zb[j * 3 + 2]);
-                    } else {
-                        const Real c0 = zb[i * 3], c1 = zb[i * 3 + 1], c2 = zb[i * 3 + 2];
-#pragma unroll
-                        for (int j = 0; j < 6; ++j)
-                            if (j <= i)
-                                acc[k][j] -= (double)(a0 * zb[j * 3] + a1 * zb[j * 3 + 1] + a2 * zb[j * 3 + 2] +
-                                                      c0 * za[j * 3] + c1 * za[j * 3 + 1] + c2 * za[j * 3 + 2]);
+        // ---- 4. pair products, PB at a time, then each owner sums its rows ---------------
+        const int npairs = nblk > 0 ? sm.cnt[nblk] : 0;
+        for (int b0 = 0, bi = 0; b0 < npairs; b0 += C::PB, ++bi) {
+            unsigned long long *touch = sm.touch + (bi & 1) * kGroups;
+            {   // thread -> pair b0 + tid % PB, rows (tid / PB) * RPT onwards
+                const int pi = b0 + tid % C::PB;
+                if (pi < npairs) {
+                    const unsigned e = sm.pairs[pi];
+                    const int la = e & 1023, lb = (e >> 10) & 1023, fl = e >> 20;
+                    Real *out = sm.prod + (pi - b0) * C::PS;
+                    if (tid < C::PB) {   // the first pair of a block in this batch marks the block
+                        const int ka = sm.oka[la], kb = sm.oka[lb];
+                        const int B = block_id(ka, kb, Kopt);
+                        if (pi == b0 || pi == sm.cnt[B])
+                            atomicOr(&touch[B % kGroups], 1ull << (B / kGroups));
                     }
+                    if (C::RPT == 6) pair_product<0, 6>(sm, la, lb, fl, out);
+                    else if (tid < C::PB) pair_product<0, 3>(sm, la, lb, fl, out);
+                    else pair_product<3, 3>(sm, la, lb, fl, out);
                 }
             }
-        }
-        if (tid < n) {
-            const int kc = tid / 6, ic = tid % 6;
-            const int B = block_id(kc, kc, Kopt);
-            for (int pi = sm.cnt[B]; pi < sm.cnt[B + 1]; ++pi) {
-                const unsigned e = sm.pairs[pi];
-                if ((e >> 20) == 1) racc += sm.rd[(e & 1023) * 6 + ic];
+            __syncthreads();
+            const int ri = qe <= 5 ? qe - 1 : 5;
+            const Real *col = sm.prod + qe;
+            const unsigned long long live = grp < kGroups ? touch[grp] & ~m_skip : 0ull;
+            // the other buffer was last read before this batch began: clear it for the next
+            if (tid < kGroups) sm.touch[((bi + 1) & 1) * kGroups + tid] = 0ull;
+#pragma unroll
+            for (int k = 0; k < kSlots; ++k) {
+                if (!((live >> k) & 1)) continue;
+                const int B = grp + kGroups * k;
+                const int p0 = max(sm.cnt[B], b0) - b0, p1 = min(sm.cnt[B + 1], b0 + C::PB) - b0;
+                if ((m_r >> k) & 1) {
+                    for (int pi = p0; pi < p1; ++pi) acc[k] += get_r(sm.prod + pi * C::PS, ri);
+                } else {   // four products per step: their loads are independent
+                    int pi = p0;
+                    for (; pi + 4 <= p1; pi += 4)
+                        acc[k] += ((double)col[pi * C::PS] + (double)col[(pi + 1) * C::PS]) +
+                                  ((double)col[(pi + 2) * C::PS] + (double)col[(pi + 3) * C::PS]);
+                    for (; pi < p1; ++pi) acc[k] += (double)col[pi * C::PS];
+                }
             }
+            __syncthreads();
         }
-        __syncthreads();
         p = q;
     }
 
@@ -389,24 +494,23 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
     const int t = blockIdx.x;
     if (!INIT) {
         double *part = a.part + W.part_off + (int64_t)(t - W.tile0) * W.part_stride;
+        double *pr = a.partr + W.partr_off + (int64_t)(t - W.tile0) * n;
 #pragma unroll
         for (int k = 0; k < kSlots; ++k) {
-            const int s_ = tid + k * kNT;
-            if (s_ >= nslot) continue;
-            const int B = s_ / 6, i = s_ - 6 * B;
-            int kA = 0;
-            while (kA + 1 < Kopt && block_id(kA + 1, kA + 1, Kopt) <= B) ++kA;
-            const int kB = kA + (B - block_id(kA, kA, Kopt));
-            const int ra = 6 * kA + i, cb = 6 * kB;
-#pragma unroll
-            for (int j = 0; j < 6; ++j) {
-                if (kA == kB && j > i) continue;
-                const int col = cb + j;
-                part[ra >= col ? packed_lower(ra, col) : packed_lower(col, ra)] = acc[k][j];
+            if ((m_skip >> k) & 1) continue;
+            const int B = grp + kGroups * k;
+            const int kA = block_row(B, Kopt);
+            if ((m_r >> k) & 1) {
+                pr[6 * kA + (qe <= 5 ? qe - 1 : 5)] = acc[k];
+                continue;
             }
+            const int kB = kA + (B - block_id(kA, kA, Kopt));
+            const int ra = 6 * kA + qe / 6, col = 6 * kB + (qe - 6 * (qe / 6));
+            part[ra >= col ? packed_lower(ra, col) : packed_lower(col, ra)] = acc[k];
         }
+    } else if (tid < n) {
+        a.partr[W.partr_off + (int64_t)(t - W.tile0) * n + tid] = racc;
     }
-    if (tid < n) a.partr[W.partr_off + (int64_t)(t - W.tile0) * n + tid] = racc;
     Facc = wave_sum(Facc);
     mdiag = wave_max(mdiag);
     const int anyfail = __syncthreads_or(fail);

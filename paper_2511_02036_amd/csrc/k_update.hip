@@ -3,8 +3,8 @@
 // One block per tile of points (same tiles as the linearisation).  The block forms the
 // trial poses Exp(dp_k) T_k of its window in LDS, then walks its points in chunks of
 // whole points (one observation per lane).  The Jacobians are recomputed at the current
-// state instead of being stored: each lane forms Hll_a (Real), and bl_a and W_a^T dp_k(a)
-// in FP64; lanes of a point sum them, factor V = Hll + lambda I = L L^T and solve
+// state instead of being stored: each lane forms Hll_a, bl_a and W_a^T dp_k(a) in FP64
+// (the same arithmetic in both precisions, since the point blocks are FP64 there too); lanes of a point sum them, factor V = Hll + lambda I = L L^T and solve
 //   dl_j = V^-1 (bl_j - q_j),   q_j = sum_a W_a^T dp_k(a),   X'_j = X_j + dl_j,
 // then every lane evaluates its observation's robust cost at (T', X') in FP64.  The block
 // writes its trial cost and its part of the gain-ratio denominator,
@@ -151,19 +151,15 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(UpdArgs a) {
                 double rho, w;
                 huber(e2 * isg, a.c.huber2[stereo], a.robust, rho, w);
                 const double omd = w * isg;
-                ObsBlocks<Real> B;
-                obs_blocks<Real>(cam, T, xc, yc, zc, eu, ev, er, stereo, (Real)omd, B);
-                point_block_fp64(cam, T, xc, yc, zc, eu, ev, er, stereo, omd, Hll, bl);
+                // W_a^T dp = R^T G c with the camera-frame motion c = dw x x + dv
+                double c0 = 0.0, c1 = 0.0, c2 = 0.0;
                 if (ka >= 0) {
-                    // W_a^T dp = M^T (A dp),  A dp = dw x x + dv
                     const double *d = sm.dp + 6 * ka;
-                    const double c0 = d[1] * zc - d[2] * yc + d[3];
-                    const double c1 = d[2] * xc - d[0] * zc + d[4];
-                    const double c2 = d[0] * yc - d[1] * xc + d[5];
-#pragma unroll
-                    for (int m = 0; m < 3; ++m)
-                        qv[m] = (double)B.M[m] * c0 + (double)B.M[3 + m] * c1 + (double)B.M[6 + m] * c2;
+                    c0 = d[1] * zc - d[2] * yc + d[3];
+                    c1 = d[2] * xc - d[0] * zc + d[4];
+                    c2 = d[0] * yc - d[1] * xc + d[5];
                 }
+                point_block_step_fp64(cam, T, xc, yc, zc, eu, ev, er, stereo, omd, c0, c1, c2, Hll, bl, qv);
             }
         }
 #pragma unroll

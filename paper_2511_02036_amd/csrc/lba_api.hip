@@ -9,6 +9,7 @@
 #include <chrono>
 #include <cmath>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "lba.h"
@@ -28,11 +29,12 @@ struct lba_ctx {
     // LM-step graphs: captured on a private stream, replayed on the caller's
     hipStream_t cap_stream = nullptr;
     struct GraphEntry {
-        std::string key;
         hipGraph_t graph;
         hipGraphExec_t exec;
+        uint64_t used;   // value of graph_clock at the last use
     };
-    std::vector<GraphEntry> graphs;   // most recently used last
+    std::unordered_map<std::string, GraphEntry> graphs;
+    uint64_t graph_clock = 0;
     // tile tuner: points per tile by optimisable-keyframe class (Kopt <= 10, <= 20, > 20)
     int64_t tuned_sig[5] = {-1, -1, -1, -1, -1};
     int tuned_ppt[3] = {0, 0, 0};
@@ -66,7 +68,7 @@ lba_status set_error(lba_ctx *ctx, lba_status st, const char *fmt, ...) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-constexpr size_t kGraphCache = 8;
+constexpr size_t kGraphCache = 1024;
 
 struct Plan {
     int nw = 0;
@@ -366,18 +368,16 @@ hipError_t collect_timing(lba_ctx *ctx) {
 
 // executable graph of one LM step for the launch arguments `key`: captured from `step` on
 // the context's private stream the first time (nothing runs during a capture) and kept in
-// a small cache, most recently used last
+// a cache of at most kGraphCache entries; the least recently used one makes room
 template <typename Fn>
 lba_status step_graph(lba_ctx *ctx, const std::string &key, Fn &&step, hipGraphExec_t *out) {
     auto &G = ctx->graphs;
-    for (size_t i = 0; i < G.size(); ++i)
-        if (G[i].key == key) {
-            lba_ctx::GraphEntry e = G[i];
-            G.erase(G.begin() + i);
-            G.push_back(e);
-            *out = e.exec;
-            return LBA_OK;
-        }
+    auto it = G.find(key);
+    if (it != G.end()) {
+        it->second.used = ++ctx->graph_clock;
+        *out = it->second.exec;
+        return LBA_OK;
+    }
     if (!ctx->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
     hipGraph_t graph = nullptr;
     HIPCHK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
@@ -396,12 +396,15 @@ lba_status step_graph(lba_ctx *ctx, const std::string &key, Fn &&step, hipGraphE
     }
     if (G.size() >= kGraphCache) {
         // every solve synchronises its stream before it returns, so only the current
-        // solve's graphs (the newest entries) can still be pending
-        (void)hipGraphExecDestroy(G.front().exec);
-        (void)hipGraphDestroy(G.front().graph);
-        G.erase(G.begin());
+        // solve's graphs (the most recently used) can still be pending
+        auto old = G.begin();
+        for (auto i = G.begin(); i != G.end(); ++i)
+            if (i->second.used < old->second.used) old = i;
+        (void)hipGraphExecDestroy(old->second.exec);
+        (void)hipGraphDestroy(old->second.graph);
+        G.erase(old);
     }
-    G.push_back({key, graph, exec});
+    G.emplace(key, lba_ctx::GraphEntry{graph, exec, ++ctx->graph_clock});
     *out = exec;
     return LBA_OK;
 }
@@ -943,8 +946,8 @@ void lba_destroy(lba_ctx *ctx) {
     if (!ctx) return;
     if (ctx->upload_pending) (void)hipEventSynchronize(ctx->upload_ev);
     for (auto &g : ctx->graphs) {
-        (void)hipGraphExecDestroy(g.exec);
-        (void)hipGraphDestroy(g.graph);
+        (void)hipGraphExecDestroy(g.second.exec);
+        (void)hipGraphDestroy(g.second.graph);
     }
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     if (ctx->upload_ev) (void)hipEventDestroy(ctx->upload_ev);
@@ -1045,8 +1048,8 @@ lba_status lba_tune(lba_ctx *ctx, const lba_problem *problem, const lba_batch *b
     auto release = [&] {
         (void)hipStreamSynchronize(s);
         for (auto &g : ctx->graphs) {
-            (void)hipGraphExecDestroy(g.exec);
-            (void)hipGraphDestroy(g.graph);
+            (void)hipGraphExecDestroy(g.second.exec);
+            (void)hipGraphDestroy(g.second.graph);
         }
         ctx->graphs.clear();
         if (ws) (void)hipFree(ws);
