@@ -213,8 +213,9 @@ __global__ __launch_bounds__(kCostThreads) void k_cost(CostArgs a) {
 }
 
 // y = J_l(xi)^T g for the SE(3) left Jacobian J_l = sum_n ad_xi^n / (n + 1)!, with
-// ad_xi = [[w^, 0], [v^, w^]] in (rotation, translation) order; the series is summed
-// by Horner's rule to 40 terms
+// ad_xi = [[w^, 0], [v^, w^]] in (rotation, translation) order.  The series is summed by
+// Horner's rule to the first N with a^N / (N + 1)! < 1e-17, a = |w|_1 + |v|_1 >= the
+// infinity norm of ad_xi (N = 0 for xi = 0), at most 60 terms.
 __device__ inline void se3_left_jacobian_t(const double *xi, const double *g, double *y) {
     double ad[36];
 #pragma unroll
@@ -229,10 +230,14 @@ __device__ inline void se3_left_jacobian_t(const double *xi, const double *g, do
             ad[(r + 3) * 6 + c] = Vh[r * 3 + c];
         }
     // J^T g = sum_n (ad^T)^n g / (n + 1)!: Horner on the vector, y = g + ad^T (g + ad^T (...)) / k
+    const double an = fabs(w0) + fabs(w1) + fabs(w2) + fabs(v0) + fabs(v1) + fabs(v2);
+    int N = 0;
+    for (double term = 1.0; N < 60 && term >= 1e-17; ++N) term *= an / (double)(N + 2);
+    if (an == 0.0) N = 0;
     double acc[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) acc[i] = g[i];
-    for (int n = 40; n >= 1; --n) {
+    for (int n = N; n >= 1; --n) {
         double t[6];
         for (int i = 0; i < 6; ++i) {
             double s = 0.0;
