@@ -4,28 +4,29 @@
 // of the reduced camera system
 //     S = Hpp + lambda I - sum_j sum_{a,b in obs(j)} W_a V_j^-1 W_b^T,
 //     r = bp - sum_j sum_{a in obs(j)} W_a V_j^-1 bl_j,
-// lives in registers for the whole tile: 14 groups of 36 threads each own one entry of
-// the 6 x 6 blocks of every 14th pair of optimisable keyframes (FP64 partial sums, so no
-// two threads ever add into the same entry and no atomics touch S or r; the unused upper
-// triangle of a diagonal block carries that camera's six entries of r).  The tile is
-// walked in chunks of whole points holding at most CO observations (CO = 256 for FP32
-// arithmetic, 128 for FP64); per chunk:
+// is assembled on chip for the whole tile.  The tile is walked in chunks of whole points
+// holding at most CO observations; per chunk:
 //   1. one thread per observation forms the residual (FP64), the robust weight and the
-//      FP64 point block Hll_a and gradient bl_a;
+//      FP64 point block Hll_a and gradient bl_a, and marks its point in its camera's bit
+//      mask;
 //   2. the threads of each point sum Hll and bl through LDS, factor
-//      V = Hll + lambda I = L L^T, and stage Z_a = W_a L^-T, D_a = Hpp_a - Z_a Z_a^T and
-//      r_a = bp_a - Z_a L^-1 bl (so W_a V^-1 W_b^T = Z_a Z_b^T) in LDS;
-//   3. every pair (a, b), a <= b, of optimisable observations of one point is counted
-//      and then placed, by camera block, into a block-sorted pair list (LDS integer
-//      atomics give each pair its slot in its block's list);
-//   4. in batches of PB pairs, one thread per pair writes the pair's signed 6 x 6
-//      contribution (-Z_a Z_b^T, or D_a and r_a for a pair of an observation with
-//      itself) to LDS in list order; every owner then adds up its entry over the
-//      contiguous run of its block.
-// At the end of the tile each owner writes its entry to the tile's partial system; a
-// separate kernel sums the partials of a window in a fixed order (no global atomics).
-// The order inside a block's run comes from the atomics, so the FP64 sums may differ
-// between runs in their last bits.
+//      V = Hll + lambda I = L L^T and stage Z_a = W_a L^-T (so W_a V^-1 W_b^T = Z_a Z_b^T);
+//      the observation's own terms D_a = Hpp_a - Z_a Z_a^T and r_a = bp_a - Z_a L^-1 bl go
+//      straight into FP64 per-camera sums in LDS (LDS atomics);
+//   3. every pair (a, b), a < b, of optimisable observations of one point is placed into
+//      a list sorted by camera block: the count of block (kA, kB) is the popcount of the
+//      two camera masks, and a pair's place is the number of the block's points before
+//      its own (a chunk with two observations of one point on one camera falls back to
+//      LDS integer atomics);
+//   4. in batches of PB pairs, one thread per pair writes -Z_a Z_b^T (lower triangle of
+//      Z_a Z_b^T + Z_b Z_a^T for two observations on one camera) to LDS in list order;
+//      14 groups of 36 threads each own one entry of every 14th camera block and add up
+//      the contiguous run of their block in FP64 registers (no two threads add into the
+//      same entry, no atomics touch S).
+// At the end of the tile each owner writes its entry, plus the per-camera sums on the
+// diagonal blocks, to the tile's partial system; a separate kernel sums the partials of
+// a window in a fixed order (no global atomics).  The per-camera sums of step 2 are
+// accumulated in no fixed order, so results may differ between runs in their last bits.
 // The gradient bp itself is not needed: the gain-ratio denominator uses
 // dp^T bp = dp^T r + sum_j q_j^T V_j^-1 bl_j (q_j = sum_a W_a^T dp), whose point part
 // the update kernel forms.
@@ -41,6 +42,7 @@ constexpr int kGroups = kLinThreads / 36;  // 14 groups of 36 threads, one block
 constexpr int kSlots = 34;                 // blocks per group (14 * 34 >= 465)
 constexpr int kMaxBlocks = 465;            // Kopt <= 30
 constexpr int kMaxN = 180;
+constexpr int kMaxOpt = 30;
 
 template <typename Real>
 struct LinCfg {
@@ -56,54 +58,23 @@ struct LinSmem {
     double *T;       // K x 12 poses
     int *opt;        // K
     Real *Z;         // CO x 18
-    Real *D;         // CO x 21   lower triangle of Hpp_a - Z_a Z_a^T (phase 1: FP64 Hll_a, 6 each)
-    double *rd;      // CO x 6    (phase 1: bl_a in the first 3) r_a
-    double *hd;      // kMaxN: r (INIT: diagonal of Hpp of the chunk)
+    double *hs;      // CO x 9    FP64 Hll_a (6) and bl_a (3) for the point sums
+    double *dacc;    // kMaxOpt x 27: per camera, sum of D_a (lower triangle, 21) and r_a (6)
+    double *hd;      // kMaxN: INIT only, diagonal of Hpp of the chunk
     unsigned *pairs; // PCAP
     Real *prod;      // PB x PS: signed 6 x 6 contribution of each pair of the current batch
     int *cnt;        // kMaxBlocks + 1 (then list offsets)
     int *cur;        // kMaxBlocks
     int *oka;        // CO: optimisable camera of the chunk observation (-1: none)
-    int *oseg;       // CO: s0 | s1 << 16 (chunk-local observation range of its point)
     int *scan;       // 16: per-wavefront totals
-    unsigned long long *touch;   // 2 x kGroups: per group, blocks with pairs in the batch
+    unsigned long long *touch;   // 2 x kGroups: per group, blocks with pairs in the batch, then
+                                 // kMaxOpt x 8: per camera, bit mask of the chunk's points it observes
     double *red;     // 16 x 2
 };
-
-// A pair of an observation with itself contributes D_a to the lower triangle of its
-// diagonal block and r_a to r.  r_a (six doubles) is parked in the unused upper triangle
-// of that pair's product: as 32-bit halves at the float positions
-// 1 2 | 3 4 | 5 8 | 9 10 | 11 15 | 16 17 (5 bits each below), or as whole doubles at the
-// positions 1 2 3 4 5 8 (4 bits each).
-constexpr unsigned long long kRPosF = 0x8c1eb5250520c41ull;
-constexpr unsigned kRPosD = 0x854321u;
-
-__device__ __forceinline__ void put_r(float *row, int i, double v) {
-    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-    row[(kRPosF >> (10 * i)) & 31] = __uint_as_float((unsigned)b);
-    row[(kRPosF >> (10 * i + 5)) & 31] = __uint_as_float((unsigned)(b >> 32));
-}
-__device__ __forceinline__ void put_r(double *row, int i, double v) { row[(kRPosD >> (4 * i)) & 15] = v; }
-__device__ __forceinline__ double get_r(const float *row, int i) {
-    const unsigned long long lo = __float_as_uint(row[(kRPosF >> (10 * i)) & 31]);
-    const unsigned long long hi = __float_as_uint(row[(kRPosF >> (10 * i + 5)) & 31]);
-    return __longlong_as_double((long long)(lo | (hi << 32)));
-}
-__device__ __forceinline__ double get_r(const double *row, int i) { return row[(kRPosD >> (4 * i)) & 15]; }
 
 // rows R0 .. R0 + NR - 1 of the signed 6 x 6 product of one pair (la, lb, flag fl)
 template <int R0, int NR, typename Real>
 __device__ __forceinline__ void pair_product(const LinSmem<Real> &sm, int la, int lb, int fl, Real *out) {
-    if (fl == 1) {   // D_a (lower triangle) and r_a
-#pragma unroll
-        for (int i = R0; i < R0 + NR; ++i)
-#pragma unroll
-            for (int j = 0; j <= i; ++j) out[i * 6 + j] = sm.D[la * 21 + i * (i + 1) / 2 + j];
-        if (R0 == 0)
-#pragma unroll
-            for (int i = 0; i < 6; ++i) put_r(out, i, sm.rd[la * 6 + i]);
-        return;
-    }
     // rows i of Z_a (and Z_b) stay in registers; rows j are streamed from LDS
     const Real *za = sm.Z + la * 18, *zb = sm.Z + lb * 18;
     Real ai[3 * NR], bi[3 * NR];
@@ -131,9 +102,6 @@ __device__ __forceinline__ void pair_product(const LinSmem<Real> &sm, int la, in
                     out[(R0 + i) * 6 + j] = -(ai[i * 3] * b0 + ai[i * 3 + 1] * b1 + ai[i * 3 + 2] * b2 +
                                               bi[i * 3] * a0 + bi[i * 3 + 1] * a1 + bi[i * 3 + 2] * a2);
         }
-        if (R0 == 0)
-#pragma unroll
-            for (int i = 0; i < 6; ++i) put_r(out, i, 0.0);
     }
 }
 
@@ -147,22 +115,21 @@ __host__ __device__ inline size_t lin_carve(unsigned char *base, int K, LinSmem<
     void *T = take(sizeof(double) * 12 * K);
     void *opt = take(sizeof(int) * K);
     void *Z = take(sizeof(Real) * C::CO * 18);
-    void *D = take(sizeof(Real) * C::CO * 21);
-    void *rd = take(sizeof(double) * C::CO * 6);
+    void *hs = take(sizeof(double) * C::CO * 9);
+    void *dacc = take(sizeof(double) * kMaxOpt * 27);
     void *pairs = take(sizeof(unsigned) * C::PCAP);
     void *prod = take(sizeof(Real) * C::PB * C::PS);
     void *cnt = take(sizeof(int) * (kMaxBlocks + 1));
     void *cur = take(sizeof(int) * kMaxBlocks);
-    void *touch = take(sizeof(unsigned long long) * 2 * kGroups);
+    void *touch = take(sizeof(unsigned long long) * (2 * kGroups + kMaxOpt * 8));
     void *oka = take(sizeof(int) * C::CO);
-    void *oseg = take(sizeof(int) * C::CO);
     void *scan = take(sizeof(int) * 16);
     void *red = take(sizeof(double) * 32);
     void *hd = take(sizeof(double) * kMaxN);
     if (s) {
-        s->T = (double *)T; s->opt = (int *)opt; s->Z = (Real *)Z; s->D = (Real *)D; s->rd = (double *)rd;
+        s->T = (double *)T; s->opt = (int *)opt; s->Z = (Real *)Z; s->hs = (double *)hs; s->dacc = (double *)dacc;
         s->pairs = (unsigned *)pairs; s->prod = (Real *)prod; s->cnt = (int *)cnt; s->cur = (int *)cur; s->touch = (unsigned long long *)touch; s->oka = (int *)oka;
-        s->oseg = (int *)oseg; s->scan = (int *)scan; s->red = (double *)red; s->hd = (double *)hd;
+        s->scan = (int *)scan; s->red = (double *)red; s->hd = (double *)hd;
     }
     return o;
 }
@@ -199,7 +166,11 @@ __device__ __forceinline__ int block_inclusive_scan(int v, int *scan, int tid) {
     if (lane == 63) scan[wave] = x;
     __syncthreads();
     int add = 0;
-    for (int w = 0; w < wave; ++w) add += scan[w];
+#pragma unroll
+    for (int w = 0; w < kNT / 64; ++w) {   // independent loads, one wait
+        const int v = scan[w];
+        add += w < wave ? v : 0;
+    }
     __syncthreads();
     return x + add;
 }
@@ -216,6 +187,7 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
     const int nblk = Kopt * (Kopt + 1) / 2;
     LinSmem<Real> sm;
     lin_carve<Real>(smem, K, &sm);
+    unsigned long long *const cm = sm.touch + 2 * kGroups;
     const double lambda = ctl.lambda;
     const double *Xs = ctl.cur ? a.X1 : a.X0;
     const int tid = threadIdx.x;
@@ -244,6 +216,8 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
         }
     }
     double racc = 0.0;   // INIT: Hpp diagonal entry tid
+    if (!INIT)
+        for (int i = tid; i < Kopt * 27; i += kNT) sm.dacc[i] = 0.0;
     __syncthreads();
 
     const CamParams cam = a.c.cam;
@@ -252,6 +226,8 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
 
     for (int p = tile.p0; p < tile.p1;) {
         // ---- chunk of whole points: <= CO observations and <= PCAP pairs ------------
+        if (!INIT)
+            for (int i = tid; i < Kopt * 8; i += kNT) cm[i] = 0ull;
         const int base = a.pt_start[p];
         const int cand = p + tid;
         int mpairs = 0, inrange = 0, obs_incl = 0;
@@ -276,13 +252,14 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
         // ---- 1. per-observation terms -------------------------------------------------
         // (only the raw observation stays in registers across the point-sum barrier; the
         //  factored blocks are recomputed from it in phase 2)
-        int s0 = 0, s1 = 0, ka = -1, kl = 0, stereo = 0;
+        int s0 = 0, s1 = 0, ka = -1, kl = 0, stereo = 0, pl = 0, dup = 0;
         bool act = false;
         double zu = 0, zv = 0, zr = 0, X0 = 0, X1 = 0, X2 = 0, omd = 0.0;
         double rho = 0.0;
         if (has) {
             const int jl = a.obs.pt[o];
             const int j = W.pt0 + jl;
+            pl = j - p;
             s0 = a.pt_start[j] - base;
             s1 = a.pt_start[j + 1] - base;
             kl = a.obs.kf[o];
@@ -303,28 +280,30 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             omd = act ? w * isg : 0.0;
             double Hll[6], bl[3];
             point_block_fp64(cam, T, xc, yc, zc, eu, ev, er, stereo, omd, Hll, bl);
-            double *hs = reinterpret_cast<double *>(sm.D);
 #pragma unroll
-            for (int i = 0; i < 6; ++i) hs[tid * 6 + i] = Hll[i];
+            for (int i = 0; i < 6; ++i) sm.hs[tid * 9 + i] = Hll[i];
 #pragma unroll
-            for (int i = 0; i < 3; ++i) sm.rd[tid * 6 + i] = bl[i];
+            for (int i = 0; i < 3; ++i) sm.hs[tid * 9 + 6 + i] = bl[i];
             if (!act) ka = -1;
             sm.oka[tid] = ka;
-            sm.oseg[tid] = s0 | (s1 << 16);
+            if (!INIT && ka >= 0) {   // the point in its camera's mask; a second hit is a duplicate
+                const unsigned long long bit = 1ull << (pl & 63);
+                dup = (__hip_atomic_fetch_or(&cm[ka * 8 + (pl >> 6)], bit, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_WORKGROUP) & bit) != 0;
+            }
         }
         Facc += rho;
-        __syncthreads();
+        const int anydup = __syncthreads_or(dup);
 
         // ---- 2. per-point sums, point factor, staged Z_a, D_a, r_a ---------------------
         double V[6] = {0, 0, 0, 0, 0, 0};
         double bs[3] = {0, 0, 0};
         if (has) {
-            const double *hs = reinterpret_cast<const double *>(sm.D);
             for (int m = s0; m < s1; ++m) {
 #pragma unroll
-                for (int i = 0; i < 6; ++i) V[i] += hs[m * 6 + i];
+                for (int i = 0; i < 6; ++i) V[i] += sm.hs[m * 9 + i];
 #pragma unroll
-                for (int i = 0; i < 3; ++i) bs[i] += sm.rd[m * 6 + i];
+                for (int i = 0; i < 3; ++i) bs[i] += sm.hs[m * 9 + 6 + i];
             }
         }
         if (INIT && tid < n) sm.hd[tid] = 0.0;
@@ -392,18 +371,21 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             bpd[2] = xc * gd[1] - yc * gd[0];
             bpd[3] = gd[0]; bpd[4] = gd[1]; bpd[5] = gd[2];
 #pragma unroll
-            for (int i = 0; i < 6; ++i)
-                sm.rd[tid * 6 + i] =
-                    bpd[i] - ((double)Zr[i * 3] * t0 + (double)Zr[i * 3 + 1] * t1 + (double)Zr[i * 3 + 2] * t2);
-#pragma unroll
             for (int i = 0; i < 18; ++i) sm.Z[tid * 18 + i] = Zr[i];
+            // the observation's own term, D_a = Hpp_a - Z_a Z_a^T and r_a = bp_a - Z_a t, goes
+            // straight into its camera's LDS sums
+            double *dst = sm.dacc + ka * 27;
             int e = 0;
 #pragma unroll
             for (int i = 0; i < 6; ++i)
 #pragma unroll
                 for (int j = 0; j <= i; ++j, ++e)
-                    sm.D[tid * 21 + e] =
-                        H[i * 6 + j] - (Zr[i * 3] * Zr[j * 3] + Zr[i * 3 + 1] * Zr[j * 3 + 1] + Zr[i * 3 + 2] * Zr[j * 3 + 2]);
+                    lds_add(dst + e, (double)(H[i * 6 + j] - (Zr[i * 3] * Zr[j * 3] + Zr[i * 3 + 1] * Zr[j * 3 + 1] +
+                                                              Zr[i * 3 + 2] * Zr[j * 3 + 2])));
+#pragma unroll
+            for (int i = 0; i < 6; ++i)
+                lds_add(dst + 21 + i,
+                        bpd[i] - ((double)Zr[i * 3] * t0 + (double)Zr[i * 3 + 1] * t1 + (double)Zr[i * 3 + 2] * t2));
         }
         for (int B = tid; B < nblk; B += kNT) {
             sm.cnt[B] = 0;
@@ -413,11 +395,29 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
         __syncthreads();
 
         // ---- 3. pair lists sorted by camera block --------------------------------------
-        if (ka >= 0) {
-            for (int b = tid; b < s1; ++b) {
-                const int kb = sm.oka[b];
-                if (kb < 0) continue;
-                atomicAdd(&sm.cnt[ka <= kb ? block_id(ka, kb, Kopt) : block_id(kb, ka, Kopt)], 1);
+        // Without duplicate (point, camera) observations the pairs of block (kA, kB) are
+        // the chunk's points seen by both cameras: their count is a popcount of the two
+        // camera masks and a pair's place in its block is the number of such points
+        // before its own, so the list is ordered by block, then point.  A chunk with a
+        // duplicate counts and places its pairs with LDS atomics instead.
+        const int nwrd = (q - p + 63) >> 6;
+        if (!anydup) {
+            for (int B = tid; B < nblk; B += kNT) {
+                const int kA = block_row(B, Kopt), kB = kA + (B - block_id(kA, kA, Kopt));
+                int c = 0;
+                if (kA != kB)
+                    for (int w = 0; w < nwrd; ++w) c += __popcll(cm[kA * 8 + w] & cm[kB * 8 + w]);
+                sm.cnt[B] = c;
+            }
+        } else if (ka >= 0) {
+            for (int b0 = tid + 1; b0 < s1; b0 += 4) {   // partners four at a time: one wait per four
+                int kb[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) kb[u] = b0 + u < s1 ? sm.oka[b0 + u] : -1;
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (kb[u] >= 0)
+                        atomicAdd(&sm.cnt[ka <= kb[u] ? block_id(ka, kb[u], Kopt) : block_id(kb[u], ka, Kopt)], 1);
             }
         }
         __syncthreads();
@@ -429,16 +429,35 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
         }
         __syncthreads();
         if (ka >= 0) {
-            for (int b = tid; b < s1; ++b) {
-                const int kb = sm.oka[b];
-                if (kb < 0) continue;
-                const int B = ka <= kb ? block_id(ka, kb, Kopt) : block_id(kb, ka, Kopt);
-                const int pos = sm.cnt[B] + atomicAdd(&sm.cur[B], 1);
-                // first = the observation on the lower camera; flag 1 = a with itself,
-                // flag 2 = two observations of one point on the same camera
-                const int first = ka <= kb ? tid : b, second = ka <= kb ? b : tid;
-                const unsigned fl = b == tid ? 1u : (ka == kb ? 2u : 0u);
-                sm.pairs[pos] = (unsigned)first | ((unsigned)second << 10) | (fl << 20);
+            const int pw = pl >> 6;
+            const unsigned long long below = (1ull << (pl & 63)) - 1ull;
+            for (int b0 = tid + 1; b0 < s1; b0 += 4) {   // partners four at a time
+                int kb[4], B[4], pos[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) kb[u] = b0 + u < s1 ? sm.oka[b0 + u] : -1;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int lo = min(ka, kb[u]), hi = max(ka, kb[u]);
+                    B[u] = block_id(lo, hi, Kopt);
+                    if (kb[u] < 0) continue;
+                    if (anydup) {
+                        pos[u] = sm.cnt[B[u]] + atomicAdd(&sm.cur[B[u]], 1);
+                    } else {
+                        int r = __popcll(cm[lo * 8 + pw] & cm[hi * 8 + pw] & below);
+                        for (int w = 0; w < pw; ++w) r += __popcll(cm[lo * 8 + w] & cm[hi * 8 + w]);
+                        pos[u] = sm.cnt[B[u]] + r;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (kb[u] < 0) continue;
+                    const int b = b0 + u;
+                    // first = the observation on the lower camera; flag 2 = two observations
+                    // of one point on the same camera
+                    const int first = ka <= kb[u] ? tid : b, second = ka <= kb[u] ? b : tid;
+                    const unsigned fl = ka == kb[u] ? 2u : 0u;
+                    sm.pairs[pos[u]] = (unsigned)first | ((unsigned)second << 10) | (fl << 20);
+                }
             }
         }
         __syncthreads();
@@ -457,7 +476,8 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
                         const int ka = sm.oka[la], kb = sm.oka[lb];
                         const int B = block_id(ka, kb, Kopt);
                         if (pi == b0 || pi == sm.cnt[B])
-                            atomicOr(&touch[B % kGroups], 1ull << (B / kGroups));
+                            __hip_atomic_fetch_or(&touch[B % kGroups], 1ull << (B / kGroups), __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_WORKGROUP);
                     }
                     if (C::RPT == 6) pair_product<0, 6>(sm, la, lb, fl, out);
                     else if (tid < C::PB) pair_product<0, 3>(sm, la, lb, fl, out);
@@ -465,9 +485,8 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
                 }
             }
             __syncthreads();
-            const int ri = qe <= 5 ? qe - 1 : 5;
             const Real *col = sm.prod + qe;
-            const unsigned long long live = grp < kGroups ? touch[grp] & ~m_skip : 0ull;
+            const unsigned long long live = grp < kGroups ? touch[grp] & ~m_skip & ~m_r : 0ull;
             // the other buffer was last read before this batch began: clear it for the next
             if (tid < kGroups) sm.touch[((bi + 1) & 1) * kGroups + tid] = 0ull;
 #pragma unroll
@@ -475,15 +494,11 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
                 if (!((live >> k) & 1)) continue;
                 const int B = grp + kGroups * k;
                 const int p0 = max(sm.cnt[B], b0) - b0, p1 = min(sm.cnt[B + 1], b0 + C::PB) - b0;
-                if ((m_r >> k) & 1) {
-                    for (int pi = p0; pi < p1; ++pi) acc[k] += get_r(sm.prod + pi * C::PS, ri);
-                } else {   // four products per step: their loads are independent
-                    int pi = p0;
-                    for (; pi + 4 <= p1; pi += 4)
-                        acc[k] += ((double)col[pi * C::PS] + (double)col[(pi + 1) * C::PS]) +
-                                  ((double)col[(pi + 2) * C::PS] + (double)col[(pi + 3) * C::PS]);
-                    for (; pi < p1; ++pi) acc[k] += (double)col[pi * C::PS];
-                }
+                int pi = p0;   // four products per step: their loads are independent
+                for (; pi + 4 <= p1; pi += 4)
+                    acc[k] += ((double)col[pi * C::PS] + (double)col[(pi + 1) * C::PS]) +
+                              ((double)col[(pi + 2) * C::PS] + (double)col[(pi + 3) * C::PS]);
+                for (; pi < p1; ++pi) acc[k] += (double)col[pi * C::PS];
             }
             __syncthreads();
         }
@@ -500,13 +515,17 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             if ((m_skip >> k) & 1) continue;
             const int B = grp + kGroups * k;
             const int kA = block_row(B, Kopt);
+            const int ri = qe <= 5 ? qe - 1 : 5;
             if ((m_r >> k) & 1) {
-                pr[6 * kA + (qe <= 5 ? qe - 1 : 5)] = acc[k];
+                pr[6 * kA + ri] = sm.dacc[kA * 27 + 21 + ri];
                 continue;
             }
             const int kB = kA + (B - block_id(kA, kA, Kopt));
-            const int ra = 6 * kA + qe / 6, col = 6 * kB + (qe - 6 * (qe / 6));
-            part[ra >= col ? packed_lower(ra, col) : packed_lower(col, ra)] = acc[k];
+            const int ie = qe / 6, je = qe - 6 * (qe / 6);
+            double v = acc[k];
+            if (kA == kB) v += sm.dacc[kA * 27 + ie * (ie + 1) / 2 + je];
+            const int ra = 6 * kA + ie, col = 6 * kB + je;
+            part[ra >= col ? packed_lower(ra, col) : packed_lower(col, ra)] = v;
         }
     } else if (tid < n) {
         a.partr[W.partr_off + (int64_t)(t - W.tile0) * n + tid] = racc;
