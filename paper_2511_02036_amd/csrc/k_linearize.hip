@@ -5,7 +5,7 @@
 //     S = Hpp + lambda I - sum_j sum_{a,b in obs(j)} W_a V_j^-1 W_b^T,
 //     r = bp - sum_j sum_{a in obs(j)} W_a V_j^-1 bl_j,
 // is assembled on chip for the whole tile.  The tile is walked in chunks of whole points
-// holding at most CO observations; per chunk:
+// holding at most CO observations (512 for FP32 arithmetic, 256 for FP64); per chunk:
 //   1. one thread per observation forms the residual (FP64), the robust weight and the
 //      FP64 point block Hll_a and gradient bl_a, and marks its point in its camera's bit
 //      mask;
@@ -46,8 +46,8 @@ constexpr int kMaxOpt = 30;
 
 template <typename Real>
 struct LinCfg {
-    static constexpr int CO = sizeof(Real) == 4 ? 256 : 128;   // observations per chunk
-    static constexpr int PCAP = 2080;                          // pairs per chunk (>= 64*65/2)
+    static constexpr int CO = sizeof(Real) == 4 ? 512 : 256;   // observations per chunk
+    static constexpr int PCAP = sizeof(Real) == 4 ? 3072 : 2080;   // pairs per chunk (>= 64*65/2)
     static constexpr int PB = sizeof(Real) == 4 ? 512 : 256;   // pair products per batch
     static constexpr int PS = 37;                              // product row stride (odd)
     static constexpr int RPT = 6 * PB / kNT;                   // product rows per thread
@@ -115,10 +115,12 @@ __host__ __device__ inline size_t lin_carve(unsigned char *base, int K, LinSmem<
     void *T = take(sizeof(double) * 12 * K);
     void *opt = take(sizeof(int) * K);
     void *Z = take(sizeof(Real) * C::CO * 18);
-    void *hs = take(sizeof(double) * C::CO * 9);
+    // the point-sum staging of phases 1-2 and the pair products of phase 4 share space
+    static_assert(sizeof(double) * C::CO * 9 <= sizeof(Real) * C::PB * C::PS, "staging overlay");
+    void *prod = take(sizeof(Real) * C::PB * C::PS);
+    void *hs = prod;
     void *dacc = take(sizeof(double) * kMaxOpt * 27);
     void *pairs = take(sizeof(unsigned) * C::PCAP);
-    void *prod = take(sizeof(Real) * C::PB * C::PS);
     void *cnt = take(sizeof(int) * (kMaxBlocks + 1));
     void *cur = take(sizeof(int) * kMaxBlocks);
     void *touch = take(sizeof(unsigned long long) * (2 * kGroups + kMaxOpt * 8));
