@@ -346,6 +346,13 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             V[5] += lambda;
             if (!chol3_inv<double>(V, Li)) fail = 1;
             lmul<double>(Li, bs[0], bs[1], bs[2], t0, t1, t2);
+            if (!INIT && tid == s0) {   // the point's factor, for this step's back-substitution
+                double *f = a.pf + 12 * (int64_t)(p + pl);
+#pragma unroll
+                for (int i = 0; i < 6; ++i) f[i] = Li[i];
+                f[6] = t0; f[7] = t1; f[8] = t2;
+                f[9] = bs[0]; f[10] = bs[1]; f[11] = bs[2];
+            }
         }
         if (ka >= 0) {
             const double *T = sm.T + kl * 12;

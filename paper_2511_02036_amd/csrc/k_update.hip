@@ -2,10 +2,11 @@
 //
 // One block per tile of points (same tiles as the linearisation).  The block forms the
 // trial poses Exp(dp_k) T_k of its window in LDS, then walks its points in chunks of
-// whole points (one observation per lane).  The Jacobians are recomputed at the current
-// state instead of being stored: each lane forms Hll_a, bl_a and W_a^T dp_k(a) in FP64
-// (the same arithmetic in both precisions, since the point blocks are FP64 there too); lanes of a point sum them, factor V = Hll + lambda I = L L^T and solve
-//   dl_j = V^-1 (bl_j - q_j),   q_j = sum_a W_a^T dp_k(a),   X'_j = X_j + dl_j,
+// whole points (one observation per lane).  Each lane forms W_a^T dp_k(a) = R^T G c in
+// FP64 at the current state (G = om P^T P, c the camera-frame motion of dp); the first
+// lane of each point sums them and back-substitutes with the point factor the
+// linearisation of the same step stored, V = L L^T, t = L^-1 bl:
+//   dl_j = L^-T (t - L^-1 q_j),   q_j = sum_a W_a^T dp_k(a),   X'_j = X_j + dl_j,
 // then every lane evaluates its observation's robust cost at (T', X') in FP64.  The block
 // writes its trial cost and its part of the gain-ratio denominator,
 //   sum_j [ dl_j^T (lambda dl_j + bl_j) + q_j^T V_j^-1 bl_j ],
@@ -22,8 +23,7 @@ struct UpdSmem {
     double *Tn;     // K x 12 trial poses
     int *opt;       // K
     double *dp;     // n
-    double *stg;    // waves x 64 x 6: Hll_a
-    double *stgd;   // waves x 64 x 6: bl_a, q_a
+    double *stgd;   // waves x 64 x 3: q_a
     double *pslot;  // waves x 64 x 4: per chunk point (dl, denominator part)
     double *red;    // waves x 3
 };
@@ -34,8 +34,7 @@ static size_t upd_lds_t(int K, int n, int waves, size_t real) {
     o = align_up_u(o + sizeof(double) * 12 * K, 16);
     o = align_up_u(o + sizeof(int) * K, 16);
     o = align_up_u(o + sizeof(double) * (n > 0 ? n : 1), 16);
-    o = align_up_u(o + sizeof(double) * waves * 64 * 6, 16);
-    o = align_up_u(o + sizeof(double) * waves * 64 * 6, 16);
+    o = align_up_u(o + sizeof(double) * waves * 64 * 3, 16);
     o = align_up_u(o + sizeof(double) * waves * 64 * 4, 16);
     o += sizeof(double) * waves * 3;
     (void)real;
@@ -58,10 +57,8 @@ __device__ inline UpdSmem<Real> carve_upd(unsigned char *base, int K, int n, int
     o = align_up_u(o + sizeof(int) * K, 16);
     s.dp = reinterpret_cast<double *>(base + o);
     o = align_up_u(o + sizeof(double) * (n > 0 ? n : 1), 16);
-    s.stg = reinterpret_cast<double *>(base + o);
-    o = align_up_u(o + sizeof(double) * waves * 64 * 6, 16);
     s.stgd = reinterpret_cast<double *>(base + o);
-    o = align_up_u(o + sizeof(double) * waves * 64 * 6, 16);
+    o = align_up_u(o + sizeof(double) * waves * 64 * 3, 16);
     s.pslot = reinterpret_cast<double *>(base + o);
     o = align_up_u(o + sizeof(double) * waves * 64 * 4, 16);
     s.red = reinterpret_cast<double *>(base + o);
@@ -99,8 +96,7 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(UpdArgs a) {
     __syncthreads();
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    double *stg = sm.stg + wave * 64 * 6;
-    double *stgd = sm.stgd + wave * 64 * 6;
+    double *stgd = sm.stgd + wave * 64 * 3;
     double *ps = sm.pslot + wave * 64 * 4;
     const int np = tile.p1 - tile.p0;
     const int wp0 = tile.p0 + (int)(((int64_t)np * wave) / waves);
@@ -126,8 +122,7 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(UpdArgs a) {
         int s0 = 0, s1 = 0, kl = 0, j = 0, stereo = 0, oct = 0;
         bool act = false;
         double zu = 0, zv = 0, zr = 0;
-        double Hll[6] = {0, 0, 0, 0, 0, 0};
-        double bl[3] = {0, 0, 0}, qv[3] = {0, 0, 0};
+        double qv[3] = {0, 0, 0};
         double X0 = 0, X1 = 0, X2 = 0;
         if (has) {
             const int jl = a.obs.pt[o];
@@ -143,71 +138,47 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(UpdArgs a) {
             X0 = Xs[3 * (int64_t)j];
             X1 = Xs[3 * (int64_t)j + 1];
             X2 = Xs[3 * (int64_t)j + 2];
-            if (act) {
+            if (act && ka >= 0) {
+                // W_a^T dp = R^T G c with the camera-frame motion c = dw x x + dv
                 const double *T = sm.T + kl * 12;
                 double xc, yc, zc, eu, ev, er;
                 const double e2 = residual(cam, T, X0, X1, X2, zu, zv, zr, stereo, xc, yc, zc, eu, ev, er);
                 const double isg = a.c.inv_sigma2[oct];
                 double rho, w;
                 huber(e2 * isg, a.c.huber2[stereo], a.robust, rho, w);
-                const double omd = w * isg;
-                // W_a^T dp = R^T G c with the camera-frame motion c = dw x x + dv
-                double c0 = 0.0, c1 = 0.0, c2 = 0.0;
-                if (ka >= 0) {
-                    const double *d = sm.dp + 6 * ka;
-                    c0 = d[1] * zc - d[2] * yc + d[3];
-                    c1 = d[2] * xc - d[0] * zc + d[4];
-                    c2 = d[0] * yc - d[1] * xc + d[5];
-                }
-                point_block_step_fp64(cam, T, xc, yc, zc, eu, ev, er, stereo, omd, c0, c1, c2, Hll, bl, qv);
+                const double *d = sm.dp + 6 * ka;
+                obs_step_q(cam, T, xc, yc, zc, stereo, w * isg, d[1] * zc - d[2] * yc + d[3],
+                           d[2] * xc - d[0] * zc + d[4], d[0] * yc - d[1] * xc + d[5], qv);
             }
         }
 #pragma unroll
-        for (int i = 0; i < 6; ++i) stg[lane * 6 + i] = Hll[i];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            stgd[lane * 6 + i] = bl[i];
-            stgd[lane * 6 + 3 + i] = qv[i];
-        }
+        for (int i = 0; i < 3; ++i) stgd[lane * 3 + i] = qv[i];
         wave_sync();
-        // the first lane of each point solves for its dl and publishes it
+        // the first lane of each point back-substitutes with the point factor the
+        // linearisation of this step left behind, and publishes dl
         if (has && lane == s0) {
-            double V[6] = {0, 0, 0, 0, 0, 0};
-            double bs[3] = {0, 0, 0}, qs[3] = {0, 0, 0};
+            double qs[3] = {0, 0, 0};
             for (int m = s0; m < s1; ++m) {
 #pragma unroll
-                for (int i = 0; i < 6; ++i) V[i] += stg[m * 6 + i];
-#pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    bs[i] += stgd[m * 6 + i];
-                    qs[i] += stgd[m * 6 + 3 + i];
-                }
+                for (int i = 0; i < 3; ++i) qs[i] += stgd[m * 3 + i];
             }
-            V[0] += lambda;
-            V[3] += lambda;
-            V[5] += lambda;
-            double Li[6];
-            double d0 = 0, d1 = 0, d2 = 0, dq = 0;
-            if (chol3_inv<double>(V, Li)) {
-                const double L0 = Li[0], L1 = Li[1], L2 = Li[2], L3 = Li[3], L4 = Li[4], L5 = Li[5];
-                // y = L^-1 (bl - q), dl = L^-T y
-                const double r0 = bs[0] - qs[0], r1 = bs[1] - qs[1], r2 = bs[2] - qs[2];
-                const double y0 = L0 * r0, y1 = L1 * r0 + L2 * r1, y2 = L3 * r0 + L4 * r1 + L5 * r2;
-                d0 = L0 * y0 + L1 * y1 + L3 * y2;
-                d1 = L2 * y1 + L4 * y2;
-                d2 = L5 * y2;
-                // q^T V^-1 bl = (L^-1 q) . (L^-1 bl)
-                const double u0 = L0 * qs[0], u1 = L1 * qs[0] + L2 * qs[1], u2 = L3 * qs[0] + L4 * qs[1] + L5 * qs[2];
-                const double v0 = L0 * bs[0], v1 = L1 * bs[0] + L2 * bs[1], v2 = L3 * bs[0] + L4 * bs[1] + L5 * bs[2];
-                dq = u0 * v0 + u1 * v1 + u2 * v2;
-            } else {
-                fail = 1;
-            }
+            const double *f = a.pf + 12 * (int64_t)j;
+            const double L0 = f[0], L1 = f[1], L2 = f[2], L3 = f[3], L4 = f[4], L5 = f[5];
+            const double t0 = f[6], t1 = f[7], t2 = f[8];
+            const double b0 = f[9], b1 = f[10], b2 = f[11];
+            // u = L^-1 q, y = L^-1 (bl - q) = t - u, dl = L^-T y
+            const double u0 = L0 * qs[0], u1 = L1 * qs[0] + L2 * qs[1], u2 = L3 * qs[0] + L4 * qs[1] + L5 * qs[2];
+            const double y0 = t0 - u0, y1 = t1 - u1, y2 = t2 - u2;
+            const double d0 = L0 * y0 + L1 * y1 + L3 * y2;
+            const double d1 = L2 * y1 + L4 * y2;
+            const double d2 = L5 * y2;
+            // q^T V^-1 bl = (L^-1 q) . (L^-1 bl)
+            const double dq = u0 * t0 + u1 * t1 + u2 * t2;
             const int slot = j - p;
             ps[slot * 4 + 0] = d0;
             ps[slot * 4 + 1] = d1;
             ps[slot * 4 + 2] = d2;
-            ps[slot * 4 + 3] = d0 * (lambda * d0 + bs[0]) + d1 * (lambda * d1 + bs[1]) + d2 * (lambda * d2 + bs[2]) + dq;
+            ps[slot * 4 + 3] = d0 * (lambda * d0 + b0) + d1 * (lambda * d1 + b1) + d2 * (lambda * d2 + b2) + dq;
         }
         // points of the chunk without observations keep their position
         const int npts = q - p;

@@ -86,7 +86,7 @@ struct Plan {
     int64_t dp_elems = 0;
     // workspace byte offsets
     size_t o_win, o_tiles, o_opt, o_kfoff, o_ptoff, o_obsoff, o_upload_end;
-    size_t o_ptstart, o_ctl, o_T, o_X0, o_X1, o_part, o_partr, o_partd, o_partu, o_red, o_redflag, o_dp,
+    size_t o_ptstart, o_ctl, o_T, o_X0, o_X1, o_part, o_partr, o_partd, o_partu, o_red, o_redflag, o_dp, o_pf,
         o_stats, o_err, total;
 };
 
@@ -263,6 +263,7 @@ lba_status build_plan(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, Pl
     pl.o_red = o;     o = align256(o + sizeof(double) * pl.red_elems);
     pl.o_redflag = o; o = align256(o + sizeof(double) * nw);
     pl.o_dp = o;      o = align256(o + sizeof(double) * pl.dp_elems);
+    pl.o_pf = o;      o = align256(o + sizeof(double) * 12 * std::max(P->n_pt, 1));
     pl.o_stats = o;   o = align256(o + sizeof(double) * LBA_STATS_LEN * nw);
     pl.o_err = o;     o = align256(o + sizeof(int32_t) * 16);
     pl.total = o;
@@ -539,6 +540,7 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
     la.part = static_cast<double *>(W_(pl.o_part));
     la.partr = static_cast<double *>(W_(pl.o_partr));
     la.partd = d_partd;
+    la.pf = static_cast<double *>(W_(pl.o_pf));
     la.waves = pl.waves;
     la.c = c;
 
@@ -574,6 +576,7 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
     ua.dp = d_dp;
     ua.obs = ob;
     ua.partu = d_partu;
+    ua.pf = static_cast<const double *>(W_(pl.o_pf));
     ua.waves = pl.waves;
     ua.c = c;
 

@@ -84,6 +84,7 @@ struct LinArgs {
     double *part;                // partial S per tile (packed lower, FP64)
     double *partr;               // FP64 partial r per tile (INIT: diagonal of Hpp)
     double *partd;               // 4 doubles per tile: F, max diag, fail, unused
+    double *pf;                  // per point: L^-1 of V (6), t = L^-1 bl (3), bl (3)
     int robust;
     int waves;
     SolveConsts c;
@@ -117,6 +118,7 @@ struct UpdArgs {
     double *X0, *X1;
     const Ctl *ctl;
     const double *dp;
+    const double *pf;            // per point factors written by the linearisation of this step
     ObsView obs;
     const uint8_t *mask;
     double *partu;               // 4 doubles per tile: F', denominator part, fail, unused
@@ -478,12 +480,10 @@ __device__ __forceinline__ void point_block_fp64(const CamParams &cam, const dou
     for (int i = 0; i < 3; ++i) bl[i] = T[i] * g0 + T[4 + i] * g1 + T[8 + i] * g2;
 }
 
-// as point_block_fp64, plus q = W^T dp = R^T G c for the camera-frame motion
-// c = dw x Xc + dv of a pose step dp = (dw, dv)
-__device__ __forceinline__ void point_block_step_fp64(const CamParams &cam, const double *T, double xc, double yc,
-                                                      double zc, double eu, double ev, double er, int stereo,
-                                                      double om, double c0, double c1, double c2, double *Hll,
-                                                      double *bl, double *q) {
+// q = W_a^T dp = R^T G c of an observation in FP64, for the camera-frame motion
+// c = dw x Xc + dv of a pose step dp = (dw, dv), G = om P^T P (P = d pi / d Xc)
+__device__ __forceinline__ void obs_step_q(const CamParams &cam, const double *T, double xc, double yc, double zc,
+                                           int stereo, double om, double c0, double c1, double c2, double *q) {
     const double iz = 1.0 / zc, st = stereo ? 1.0 : 0.0;
     const double p00 = cam.fx * iz, p02 = -cam.fx * xc * iz * iz;
     const double p11 = cam.fy * iz, p12 = -cam.fy * yc * iz * iz;
@@ -491,27 +491,9 @@ __device__ __forceinline__ void point_block_step_fp64(const CamParams &cam, cons
     const double G00 = om * (p00 * p00 * (1.0 + st)), G02 = om * (p00 * p02 + st * p00 * p22);
     const double G11 = om * (p11 * p11), G12 = om * (p11 * p12);
     const double G22 = om * (p02 * p02 + p12 * p12 + st * p22 * p22);
-    const double g0 = om * (p00 * eu + st * p00 * er), g1 = om * (p11 * ev);
-    const double g2 = om * (p02 * eu + p12 * ev + st * p22 * er);
-    double M[9];   // G R
+    const double g0 = G00 * c0 + G02 * c2, g1 = G11 * c1 + G12 * c2, g2 = G02 * c0 + G12 * c1 + G22 * c2;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const double r0 = T[c], r1 = T[4 + c], r2 = T[8 + c];
-        M[c] = G00 * r0 + G02 * r2;
-        M[3 + c] = G11 * r1 + G12 * r2;
-        M[6 + c] = G02 * r0 + G12 * r1 + G22 * r2;
-    }
-    Hll[0] = T[0] * M[0] + T[4] * M[3] + T[8] * M[6];
-    Hll[1] = T[0] * M[1] + T[4] * M[4] + T[8] * M[7];
-    Hll[2] = T[0] * M[2] + T[4] * M[5] + T[8] * M[8];
-    Hll[3] = T[1] * M[1] + T[5] * M[4] + T[9] * M[7];
-    Hll[4] = T[1] * M[2] + T[5] * M[5] + T[9] * M[8];
-    Hll[5] = T[2] * M[2] + T[6] * M[5] + T[10] * M[8];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        bl[i] = T[i] * g0 + T[4 + i] * g1 + T[8 + i] * g2;
-        q[i] = M[i] * c0 + M[3 + i] * c1 + M[6 + i] * c2;
-    }
+    for (int i = 0; i < 3; ++i) q[i] = T[i] * g0 + T[4 + i] * g1 + T[8 + i] * g2;
 }
 
 // Hll (6 upper entries) and bl of an observation
