@@ -63,18 +63,20 @@ hipError_t launch_setup(const MiscArgs &a, int n_windows, hipStream_t s) {
     return hipGetLastError();
 }
 
+// grid (x, window): the blocks of row y check window y's observations; all blocks
+// together check the poses, points and per-point observation counts
 __global__ void k_validate(MiscArgs a) {
-    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    const int w = blockIdx.y;
+    const int64_t o0 = a.obs_off_dev[w], o1 = a.obs_off_dev[w + 1];
+    const int K = a.kf_off_dev[w + 1] - a.kf_off_dev[w];
+    const int M = a.pt_off_dev[w + 1] - a.pt_off_dev[w];
     int32_t err = 0;
-    for (int64_t o = tid; o < a.obs.n_obs; o += nth) {
-        const int w = find_window(a.obs_off_dev, a.c.n_windows, (int)o);
-        const int K = a.kf_off_dev[w + 1] - a.kf_off_dev[w];
-        const int M = a.pt_off_dev[w + 1] - a.pt_off_dev[w];
+    for (int64_t o = o0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < o1;
+         o += (int64_t)gridDim.x * blockDim.x) {
         const int kf = a.obs.kf[o], pt = a.obs.pt[o];
         if (kf < 0 || kf >= K) err |= ERR_KF_INDEX;
         if (pt < 0 || pt >= M) err |= ERR_PT_INDEX;
-        if (o > a.obs_off_dev[w] && pt < a.obs.pt[o - 1]) err |= ERR_UNSORTED;
+        if (o > o0 && pt < a.obs.pt[o - 1]) err |= ERR_UNSORTED;
         if (a.obs.oct[o] >= a.n_levels) err |= ERR_OCTAVE;
         const int ty = a.obs.type[o];
         if (ty > 1) err |= ERR_TYPE;
@@ -84,6 +86,8 @@ __global__ void k_validate(MiscArgs a) {
         else load_z<double>(a.obs, (int)o, u, v, ur);
         if (!isfinite(u) || !isfinite(v) || (ty == 1 && !isfinite(ur))) err |= ERR_NONFINITE_OBS;
     }
+    const int64_t tid = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t nth = (int64_t)gridDim.x * gridDim.y * blockDim.x;
     if (a.T_in)
         for (int64_t i = tid; i < (int64_t)a.n_kf * 12; i += nth)
             if (!isfinite(a.T_in[i])) err |= ERR_NONFINITE_POSE;
@@ -95,21 +99,33 @@ __global__ void k_validate(MiscArgs a) {
     if (err) atomicOr(a.err, err);
 }
 
-hipError_t launch_validate(const MiscArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_validate, dim3(1024), dim3(256), 0, s, a);
+// blocks per window row of the (x, window) grids: enough for the largest window
+static int row_blocks(int64_t max_obs) {
+    int64_t bx = (max_obs + 2047) / 2048;
+    return (int)(bx < 1 ? 1 : (bx > 128 ? 128 : bx));
+}
+
+hipError_t launch_validate(const MiscArgs &a, int n_windows, int64_t max_obs, hipStream_t s) {
+    if (n_windows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_validate, dim3(row_blocks(max_obs), n_windows), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
-// chi-square outlier test of every observation at the current state
+// chi-square outlier test of every observation at the current state; grid (x, window).
+// With a.count set, each wavefront also adds its number of flagged observations to the
+// window's control block (integer atomics: the total does not depend on their order).
 __global__ void k_flags(MiscArgs a) {
-    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t o = tid; o < a.obs.n_obs; o += nth) {
-        const int w = find_window(a.obs_off_dev, a.c.n_windows, (int)o);
-        const Ctl &c = a.ctl[w];
-        const double *X = c.cur ? a.X1 : a.X0;
-        const int kf = a.kf_off_dev[w] + a.obs.kf[o];
-        const int64_t pt = a.pt_off_dev[w] + a.obs.pt[o];
+    const int w = blockIdx.y;
+    const int64_t o0 = a.obs_off_dev[w], o1 = a.obs_off_dev[w + 1];
+    Ctl &c = a.ctl[w];
+    const double *X = c.cur ? a.X1 : a.X0;
+    const int kf0 = a.kf_off_dev[w];
+    const int64_t pt0 = a.pt_off_dev[w];
+    int nflag = 0;
+    for (int64_t o = o0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < o1;
+         o += (int64_t)gridDim.x * blockDim.x) {
+        const int kf = kf0 + a.obs.kf[o];
+        const int64_t pt = pt0 + a.obs.pt[o];
         const int stereo = a.obs.type[o];
         double u, v, ur;
         if (a.obs.z_f32) load_z<float>(a.obs, (int)o, u, v, ur);
@@ -118,22 +134,26 @@ __global__ void k_flags(MiscArgs a) {
         const double e2 = residual(a.c.cam, a.T + 12 * (int64_t)kf, X[3 * pt], X[3 * pt + 1], X[3 * pt + 2],
                                    u, v, ur, stereo, xc, yc, zc, eu, ev, er);
         const double s = e2 * a.c.inv_sigma2[a.obs.oct[o]];
-        a.flags[o] = (s > a.c.chi2[stereo] || zc <= 0.0) ? 1 : 0;
+        const int f = (s > a.c.chi2[stereo] || zc <= 0.0) ? 1 : 0;
+        a.flags[o] = (uint8_t)f;
+        nflag += f;
+    }
+    if (a.count) {
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) nflag += __shfl_xor(nflag, d, 64);
+        if ((threadIdx.x & 63) == 0 && nflag) atomicAdd(&c.n_outliers, nflag);
     }
 }
 
-hipError_t launch_flags(const MiscArgs &a, hipStream_t s) {
-    if (a.obs.n_obs <= 0) return hipSuccess;
-    int blocks = (a.obs.n_obs + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_flags, dim3(blocks), dim3(256), 0, s, a);
+hipError_t launch_flags(const MiscArgs &a, int n_windows, int64_t max_obs, hipStream_t s) {
+    if (a.obs.n_obs <= 0 || n_windows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_flags, dim3(row_blocks(max_obs), n_windows), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
 // copy-out of the final state and per-window statistics: grid (x, window); every block
 // copies a slice of its window's points, block x == 0 also the poses and the statistics
 __global__ __launch_bounds__(256) void k_finalize(MiscArgs a) {
-    __shared__ int cnt[4];
     const int w = blockIdx.y;
     const WinInfo W = a.win[w];
     const Ctl c = a.ctl[w];
@@ -145,14 +165,8 @@ __global__ __launch_bounds__(256) void k_finalize(MiscArgs a) {
     if (blockIdx.x != 0) return;
     for (int i = threadIdx.x; i < 12 * W.K; i += blockDim.x)
         a.T_out[12 * (int64_t)W.kf0 + i] = a.T[12 * (int64_t)W.kf0 + i];
-    int n = 0;
-    for (int i = threadIdx.x; i < W.N; i += blockDim.x) n += a.flags[(int64_t)W.ob0 + i];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o, 64);
-    if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = n;
-    __syncthreads();
     if (threadIdx.x == 0) {
-        const int tot = cnt[0] + cnt[1] + cnt[2] + cnt[3];
+        const int tot = c.n_outliers;
         double *st = a.stats + 12 * (int64_t)w;
         st[0] = c.F_initial;
         st[1] = c.F;

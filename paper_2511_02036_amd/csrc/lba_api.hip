@@ -72,6 +72,7 @@ constexpr size_t kGraphCache = 1024;
 
 struct Plan {
     int nw = 0;
+    int64_t max_obs = 0;
     bool mixed = false;
     int waves = 4;
     std::vector<WinInfo> win;
@@ -219,6 +220,7 @@ lba_status build_plan(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, Pl
         maxK = std::max(maxK, W.K);
         maxn = std::max(maxn, W.n);
         pl.max_En = std::max(pl.max_En, W.E + W.n);
+        pl.max_obs = std::max<int64_t>(pl.max_obs, W.N);
     }
     if (red > INT32_MAX) return set_error(ctx, LBA_ERR_UNSUPPORTED, "batch too large");
     pl.part_elems = std::max<int64_t>(part, 1);
@@ -517,7 +519,7 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
     m.c = c;
 
     HIPCHK(timed(ctx, LBA_KCLASS_SETUP, s, [&] { return launch_setup(m, nw, s); }));
-    HIPCHK(timed(ctx, LBA_KCLASS_VALIDATE, s, [&] { return launch_validate(m, s); }));
+    HIPCHK(timed(ctx, LBA_KCLASS_VALIDATE, s, [&] { return launch_validate(m, nw, pl.max_obs, s); }));
     HIPCHK(hipMemcpyAsync(down, d_err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     int32_t in_err;
@@ -603,7 +605,8 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
         const int iters = round == 1 ? opt.iters_round1 : opt.iters_round2;
         const uint8_t *mask = nullptr;
         if (round == 2) {
-            HIPCHK(timed(ctx, LBA_KCLASS_FLAGS, s, [&] { return launch_flags(m, s); }));
+            m.count = 0;
+            HIPCHK(timed(ctx, LBA_KCLASS_FLAGS, s, [&] { return launch_flags(m, nw, pl.max_obs, s); }));
             mask = R->outlier;
         }
         const int robust = round == 1 ? 1 : (opt.round2_robust ? 1 : 0);
@@ -664,7 +667,8 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
             nsteps = std::min(need, max_steps - steps_done);
         }
     }
-    HIPCHK(timed(ctx, LBA_KCLASS_FLAGS, s, [&] { return launch_flags(m, s); }));
+    m.count = 1;
+    HIPCHK(timed(ctx, LBA_KCLASS_FLAGS, s, [&] { return launch_flags(m, nw, pl.max_obs, s); }));
     HIPCHK(timed(ctx, LBA_KCLASS_FINALIZE, s, [&] { return launch_finalize(m, nw, s); }));
     if (R->stats) {
         HIPCHK(hipMemcpyAsync(down, d_stats, sizeof(double) * LBA_STATS_LEN * nw, hipMemcpyDeviceToHost, s));
@@ -683,6 +687,7 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
 // ------------------------------------------------------------------------------------
 struct CostPlan {
     int nw = 0;
+    int64_t max_obs = 0;
     int maxK = 0;
     std::vector<CostWin> win;
     std::vector<Tile> tiles;
@@ -752,6 +757,7 @@ lba_status build_cost_plan(lba_ctx *ctx, const lba_problem *P, const lba_batch *
             cp.tiles.push_back(T);
         }
         W.g_off = g;
+        cp.max_obs = std::max<int64_t>(cp.max_obs, W.N);
         g += (int64_t)W.ntiles * W.K * 6;
         cp.maxK = std::max(cp.maxK, W.K);
     }
@@ -842,7 +848,7 @@ lba_status cost_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, boo
 
     HIPCHK(timed(ctx, LBA_KCLASS_SETUP, s, [&] { return launch_setup(m, nw, s); }));
     if (ctx->opt.check_inputs) {
-        HIPCHK(timed(ctx, LBA_KCLASS_VALIDATE, s, [&] { return launch_validate(m, s); }));
+        HIPCHK(timed(ctx, LBA_KCLASS_VALIDATE, s, [&] { return launch_validate(m, nw, cp.max_obs, s); }));
         HIPCHK(hipMemcpyAsync(down, d_err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         int32_t in_err;

@@ -165,6 +165,7 @@ struct MiscArgs {
     int32_t *err;
     int32_t n_kf, n_pt, n_levels;
     int32_t round;
+    int32_t count;               // k_flags: add the flagged observations to Ctl::n_outliers
     SolveConsts c;
 };
 
@@ -209,8 +210,8 @@ hipError_t launch_cholesky(const CholArgs &a, int n_windows, size_t lds, hipStre
 hipError_t launch_decide(const DecideArgs &a, int n_windows, hipStream_t s);
 hipError_t launch_init_reduce(const InitReduceArgs &a, int n_windows, hipStream_t s);
 hipError_t launch_setup(const MiscArgs &a, int n_windows, hipStream_t s);
-hipError_t launch_validate(const MiscArgs &a, hipStream_t s);
-hipError_t launch_flags(const MiscArgs &a, hipStream_t s);
+hipError_t launch_validate(const MiscArgs &a, int n_windows, int64_t max_obs, hipStream_t s);
+hipError_t launch_flags(const MiscArgs &a, int n_windows, int64_t max_obs, hipStream_t s);
 hipError_t launch_finalize(const MiscArgs &a, int n_windows, hipStream_t s);
 hipError_t launch_cost(const CostArgs &a, int ntiles, int max_k, bool backward, hipStream_t s);
 hipError_t launch_cost_reduce(const CostArgs &a, int n_windows, bool backward, hipStream_t s);
