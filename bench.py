@@ -275,6 +275,7 @@ def main():
     ap.add_argument("--workload", default="c5_batched_mixed", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-window plain FP64 comparison")
+    ap.add_argument("--no-tune", action="store_true", help="batched workloads: skip the tile tuner")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 256 MiB device to device once (a kernel of known traffic that "
                          "calibrates hardware byte counters read by a profiler)")
@@ -309,8 +310,14 @@ def main():
     dev = torch.device("cuda:0")
     ctx = lba.Context(device=0, precision=spec["precision"])
     prob = lba.DeviceProblem(data, device=dev, z_f32=z_f32)
-    solver = lba.Solver(ctx, prob)
     stream = torch.cuda.current_stream(dev)
+    tuned = None
+    if len(windows) > 1 and not args.no_tune:
+        # the tile tuner of the batched form (short solves; its table is kept in the context)
+        t_tune = time.perf_counter()
+        tuned = ctx.tune(prob, stream)
+        print(f"bench: tile table {tuned} tuned in {time.perf_counter() - t_tune:.1f} s", file=sys.stderr, flush=True)
+    solver = lba.Solver(ctx, prob)
     print(f"bench: workload={args.workload} windows={len(windows)} obs={prob.obs_kf.shape[0]} "
           f"(generated in {time.perf_counter() - t_gen:.1f} s) warmup={args.warmup} steps={args.steps}",
           file=sys.stderr, flush=True)
@@ -379,7 +386,8 @@ def main():
         "config": {"workload": args.workload, "description": spec["desc"], "windows": len(windows),
                    "keyframes": int(sum(s["K"] for s in shapes)), "points": int(sum(s["M"] for s in shapes)),
                    "observations": int(sum(s["N"] for s in shapes)),
-                   "lm_iterations_per_step": iters // args.steps},
+                   "lm_iterations_per_step": iters // args.steps,
+                   "points_per_tile_by_kopt_class": tuned},
         "graph_replay": {"value": giters / gel, "ms_per_step": 1e3 * gel / args.steps,
                          "note": "the timed steps repeated with each LM step replayed from its HIP graph "
                                  "(value above: kernels launched one by one between HIP events)"},
