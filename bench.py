@@ -325,6 +325,10 @@ def main():
     for _ in range(args.warmup):
         solver.run(stream)
     torch.cuda.synchronize()
+    # two small tagged kernels bracket the timed steps in a profiler's kernel trace
+    marker = torch.ones(1, device=dev)
+    marker.mul_(3.0)
+    torch.cuda.synchronize()
     ctx.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -336,6 +340,8 @@ def main():
     el = time.perf_counter() - t0
     prof = ctx.profile_read()
     ctx.profile(False)
+    marker.div_(3.0)
+    torch.cuda.synchronize()
     print(f"bench: timed {args.steps} steps in {el:.3f} s", file=sys.stderr, flush=True)
     # the same steps again without per-kernel events: each LM step replays its captured graph
     solver.run(stream)

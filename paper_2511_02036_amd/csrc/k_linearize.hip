@@ -119,6 +119,10 @@ __host__ __device__ inline size_t lin_carve(unsigned char *base, int K, LinSmem<
     static_assert(sizeof(double) * C::CO * 9 <= sizeof(Real) * C::PB * C::PS, "staging overlay");
     void *prod = take(sizeof(Real) * C::PB * C::PS);
     void *hs = prod;
+    // ... and so do, after it, the chunk's point positions (512 x 3) and observation
+    // ranges (513), see the kernel
+    static_assert(sizeof(double) * (C::CO * 9 + kNT * 3) + sizeof(int) * (kNT + 1) <=
+                      sizeof(Real) * C::PB * C::PS, "staging overlay");
     void *dacc = take(sizeof(double) * kMaxOpt * 27);
     void *pairs = take(sizeof(unsigned) * C::PCAP);
     void *cnt = take(sizeof(int) * (kMaxBlocks + 1));
@@ -190,6 +194,8 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
     LinSmem<Real> sm;
     lin_carve<Real>(smem, K, &sm);
     unsigned long long *const cm = sm.touch + 2 * kGroups;
+    double *const xs = sm.hs + C::CO * 9;               // chunk point positions
+    int *const pst = reinterpret_cast<int *>(xs + 3 * kNT);   // chunk-local observation starts
     const double lambda = ctl.lambda;
     const double *Xs = ctl.cur ? a.X1 : a.X0;
     const int tid = threadIdx.x;
@@ -247,35 +253,51 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             fail = 1;
             break;
         }
-        const int nob = a.pt_start[q] - base;
-        const bool has = tid < nob;
+        // the chunk's point ranges and positions go to LDS (coalesced, and independent of
+        // the observation loads below, so both are in flight together)
+        const int np = q - p;
+        if (tid < np) {
+            pst[tid + 1] = obs_incl;
+            xs[3 * tid] = Xs[3 * (int64_t)cand];
+            xs[3 * tid + 1] = Xs[3 * (int64_t)cand + 1];
+            xs[3 * tid + 2] = Xs[3 * (int64_t)cand + 2];
+        }
+        if (tid == 0) pst[0] = 0;
         const int o = base + tid;
+        const bool inb = o < a.obs.n_obs;
+        int jl = 0, kl = 0, stereo = 0, oct = 0;
+        bool act = false;
+        double zu = 0, zv = 0, zr = 0;
+        if (inb) {
+            jl = a.obs.pt[o];
+            kl = a.obs.kf[o];
+            act = !a.mask || !a.mask[o];
+            stereo = a.obs.type[o];
+            oct = a.obs.oct[o];
+            load_z<ZT>(a.obs, o, zu, zv, zr);
+        }
+        __syncthreads();
+        const int nob = pst[np];
+        const bool has = tid < nob;
 
         // ---- 1. per-observation terms -------------------------------------------------
         // (only the raw observation stays in registers across the point-sum barrier; the
         //  factored blocks are recomputed from it in phase 2)
-        int s0 = 0, s1 = 0, ka = -1, kl = 0, stereo = 0, pl = 0, dup = 0;
-        bool act = false;
-        double zu = 0, zv = 0, zr = 0, X0 = 0, X1 = 0, X2 = 0, omd = 0.0;
+        int s0 = 0, s1 = 0, ka = -1, pl = 0, dup = 0;
+        double X0 = 0, X1 = 0, X2 = 0, omd = 0.0;
         double rho = 0.0;
         if (has) {
-            const int jl = a.obs.pt[o];
-            const int j = W.pt0 + jl;
-            pl = j - p;
-            s0 = a.pt_start[j] - base;
-            s1 = a.pt_start[j + 1] - base;
-            kl = a.obs.kf[o];
+            pl = W.pt0 + jl - p;
+            s0 = pst[pl];
+            s1 = pst[pl + 1];
             ka = sm.opt[kl];
-            act = !a.mask || !a.mask[o];
-            stereo = a.obs.type[o];
-            load_z<ZT>(a.obs, o, zu, zv, zr);
-            X0 = Xs[3 * (int64_t)j];
-            X1 = Xs[3 * (int64_t)j + 1];
-            X2 = Xs[3 * (int64_t)j + 2];
+            X0 = xs[3 * pl];
+            X1 = xs[3 * pl + 1];
+            X2 = xs[3 * pl + 2];
             const double *T = sm.T + kl * 12;
             double xc, yc, zc, eu, ev, er;
             const double e2 = residual(cam, T, X0, X1, X2, zu, zv, zr, stereo, xc, yc, zc, eu, ev, er);
-            const double isg = a.c.inv_sigma2[a.obs.oct[o]];
+            const double isg = a.c.inv_sigma2[oct];
             double w;
             huber(e2 * isg, a.c.huber2[stereo], a.robust, rho, w);
             if (!act) rho = 0.0;
