@@ -25,6 +25,8 @@ struct UpdSmem {
     double *dp;     // n
     double *stgd;   // waves x 64 x 3: q_a
     double *pslot;  // waves x 64 x 4: per chunk point (dl, denominator part)
+    double *xs;     // waves x 64 x 3: positions of the chunk's points
+    int *pst;       // waves x 65: chunk-local first observation of each point
     double *red;    // waves x 3
 };
 
@@ -36,6 +38,8 @@ static size_t upd_lds_t(int K, int n, int waves, size_t real) {
     o = align_up_u(o + sizeof(double) * (n > 0 ? n : 1), 16);
     o = align_up_u(o + sizeof(double) * waves * 64 * 3, 16);
     o = align_up_u(o + sizeof(double) * waves * 64 * 4, 16);
+    o = align_up_u(o + sizeof(double) * waves * 64 * 3, 16);
+    o = align_up_u(o + sizeof(int) * waves * 65, 16);
     o += sizeof(double) * waves * 3;
     (void)real;
     return o;
@@ -61,6 +65,10 @@ __device__ inline UpdSmem<Real> carve_upd(unsigned char *base, int K, int n, int
     o = align_up_u(o + sizeof(double) * waves * 64 * 3, 16);
     s.pslot = reinterpret_cast<double *>(base + o);
     o = align_up_u(o + sizeof(double) * waves * 64 * 4, 16);
+    s.xs = reinterpret_cast<double *>(base + o);
+    o = align_up_u(o + sizeof(double) * waves * 64 * 3, 16);
+    s.pst = reinterpret_cast<int *>(base + o);
+    o = align_up_u(o + sizeof(int) * waves * 65, 16);
     s.red = reinterpret_cast<double *>(base + o);
     return s;
 }
@@ -97,6 +105,8 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(UpdArgs a) {
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double *stgd = sm.stgd + wave * 64 * 3;
+    double *xs = sm.xs + wave * 64 * 3;
+    int *pst = sm.pst + wave * 65;
     double *ps = sm.pslot + wave * 64 * 4;
     const int np = tile.p1 - tile.p0;
     const int wp0 = tile.p0 + (int)(((int64_t)np * wave) / waves);
@@ -108,36 +118,54 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(UpdArgs a) {
     for (int p = wp0; p < wp1;) {
         const int base = a.pt_start[p];
         const int cand = p + lane;
-        int ok = 0;
-        if (cand < wp1) ok = (a.pt_start[cand + 1] - base) <= kMaxObsPerPoint;
+        int ok = 0, e = 0;
+        if (cand < wp1) {
+            e = a.pt_start[cand + 1] - base;
+            ok = e <= kMaxObsPerPoint;
+        }
         const int q = p + __popcll(__ballot(ok));
         if (q == p) {   // a point with more observations than one wavefront: not solvable here
             fail = 1;
             break;
         }
-        const int nob = a.pt_start[q] - base;
-        const bool has = lane < nob;
+        // the chunk's point ranges and positions into this wavefront's LDS rows, loaded
+        // together with the observations
+        const int npts = q - p;
+        if (lane < npts) {
+            pst[lane + 1] = e;
+            xs[3 * lane] = Xs[3 * (int64_t)cand];
+            xs[3 * lane + 1] = Xs[3 * (int64_t)cand + 1];
+            xs[3 * lane + 2] = Xs[3 * (int64_t)cand + 2];
+        }
+        if (lane == 0) pst[0] = 0;
         const int o = base + lane;
-
-        int s0 = 0, s1 = 0, kl = 0, j = 0, stereo = 0, oct = 0;
+        int jl = 0, kl = 0, stereo = 0, oct = 0;
         bool act = false;
         double zu = 0, zv = 0, zr = 0;
-        double qv[3] = {0, 0, 0};
-        double X0 = 0, X1 = 0, X2 = 0;
-        if (has) {
-            const int jl = a.obs.pt[o];
-            j = W.pt0 + jl;
-            s0 = a.pt_start[j] - base;
-            s1 = a.pt_start[j + 1] - base;
+        if (o < a.obs.n_obs) {
+            jl = a.obs.pt[o];
             kl = a.obs.kf[o];
-            const int ka = sm.opt[kl];
             act = !a.mask || !a.mask[o];
             stereo = a.obs.type[o];
             oct = a.obs.oct[o];
             load_z<ZT>(a.obs, o, zu, zv, zr);
-            X0 = Xs[3 * (int64_t)j];
-            X1 = Xs[3 * (int64_t)j + 1];
-            X2 = Xs[3 * (int64_t)j + 2];
+        }
+        wave_sync();
+        const int nob = pst[npts];
+        const bool has = lane < nob;
+
+        int s0 = 0, s1 = 0, j = 0, pl = 0;
+        double qv[3] = {0, 0, 0};
+        double X0 = 0, X1 = 0, X2 = 0;
+        if (has) {
+            j = W.pt0 + jl;
+            pl = j - p;
+            s0 = pst[pl];
+            s1 = pst[pl + 1];
+            const int ka = sm.opt[kl];
+            X0 = xs[3 * pl];
+            X1 = xs[3 * pl + 1];
+            X2 = xs[3 * pl + 2];
             if (act && ka >= 0) {
                 // W_a^T dp = R^T G c with the camera-frame motion c = dw x x + dv
                 const double *T = sm.T + kl * 12;
@@ -181,8 +209,7 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(UpdArgs a) {
             ps[slot * 4 + 3] = d0 * (lambda * d0 + b0) + d1 * (lambda * d1 + b1) + d2 * (lambda * d2 + b2) + dq;
         }
         // points of the chunk without observations keep their position
-        const int npts = q - p;
-        if (lane < npts && a.pt_start[p + lane + 1] == a.pt_start[p + lane]) {
+        if (lane < npts && pst[lane + 1] == pst[lane]) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) ps[lane * 4 + i] = 0.0;
         }
@@ -190,9 +217,9 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(UpdArgs a) {
         // one lane per point writes X' and its part of the denominator
         if (lane < npts) {
             const int64_t jp = p + lane;
-            Xn[3 * jp] = Xs[3 * jp] + ps[lane * 4];
-            Xn[3 * jp + 1] = Xs[3 * jp + 1] + ps[lane * 4 + 1];
-            Xn[3 * jp + 2] = Xs[3 * jp + 2] + ps[lane * 4 + 2];
+            Xn[3 * jp] = xs[3 * lane] + ps[lane * 4];
+            Xn[3 * jp + 1] = xs[3 * lane + 1] + ps[lane * 4 + 1];
+            Xn[3 * jp + 2] = xs[3 * lane + 2] + ps[lane * 4 + 2];
             den += ps[lane * 4 + 3];
         }
         // trial cost of every active observation at (T', X')
