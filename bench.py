@@ -102,16 +102,18 @@ def kernel_bytes_and_flops(cls, s, n_tiles, real_bytes, z_bytes):
     shape s.  Bytes: what the kernel must read and write once (observation records,
     point states, poses, its outputs).  Flops: counted from the formulas the kernel
     evaluates (residual + Jacobian + blocks ~420 per observation, point factor ~60 per
-    point, 216 per ordered pair of a point's observations on optimisable keyframes)."""
+    point, 216 per ordered pair of a point's observations on optimisable keyframes; the
+    update kernel ~150 per observation and ~60 per point)."""
     K, M, N, n = s["K"], s["M"], s["N"], 6 * s["Kopt"]
     E = n * (n + 1) // 2
     obs_rec = 4 + 4 + 3 * z_bytes + 1 + 1          # kf, pt, u/v/uR, type, octave
     if cls == "linearize":
-        b = N * obs_rec + M * (24 + 4) + n_tiles * (K * 100 + (E + 2 * n) * real_bytes + 32)
+        # + the point factor (96 B) each point leaves for the update kernel
+        b = N * obs_rec + M * (24 + 4 + 96) + n_tiles * (K * 100 + (E + 2 * n) * real_bytes + 32)
         return b, 420 * N + 60 * M + 216 * s["pairs"]
     if cls == "update":
-        b = N * obs_rec + M * (24 + 24 + 4) + n_tiles * (K * 100 + n * 8 + 32)
-        return b, 330 * N + 60 * M
+        b = N * obs_rec + M * (24 + 24 + 4 + 96) + n_tiles * (K * 100 + n * 8 + 32)
+        return b, 150 * N + 60 * M
     if cls == "reduce":
         return n_tiles * (E + 2 * n) * real_bytes + (E + 2 * n) * 8, n_tiles * (E + 2 * n)
     if cls == "cholesky":
