@@ -185,7 +185,8 @@ template <typename Real, typename ZT, bool INIT>
 __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
     using C = LinCfg<Real>;
     extern __shared__ __align__(16) unsigned char smem[];
-    const Tile tile = a.tiles[blockIdx.x];
+    const int t = a.order[blockIdx.x];
+    const Tile tile = a.tiles[t];
     const WinInfo W = a.win[tile.win];
     const Ctl ctl = a.ctl[tile.win];
     if (!INIT && !ctl.running) return;
@@ -537,7 +538,6 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
     }
 
     // ---- write-out: owned rows of S, r, and the tile's scalars ----------------------
-    const int t = blockIdx.x;
     if (!INIT) {
         double *part = a.part + W.part_off + (int64_t)(t - W.tile0) * W.part_stride;
         double *pr = a.partr + W.partr_off + (int64_t)(t - W.tile0) * n;

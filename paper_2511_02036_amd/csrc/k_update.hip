@@ -76,7 +76,8 @@ __device__ inline UpdSmem<Real> carve_upd(unsigned char *base, int K, int n, int
 template <typename Real, typename ZT>
 __global__ __launch_bounds__(kUpdThreads) void k_update(UpdArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const Tile tile = a.tiles[blockIdx.x];
+    const int tt = a.order[blockIdx.x];
+    const Tile tile = a.tiles[tt];
     const WinInfo W = a.win[tile.win];
     const Ctl ctl = a.ctl[tile.win];
     if (!ctl.running) return;
@@ -252,7 +253,7 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(UpdArgs a) {
             D += sm.red[w * 3 + 1];
             fl = fmax(fl, sm.red[w * 3 + 2]);
         }
-        const int t = blockIdx.x;
+        const int t = tt;
         a.partu[4 * t] = F;
         a.partu[4 * t + 1] = D;
         a.partu[4 * t + 2] = fl;

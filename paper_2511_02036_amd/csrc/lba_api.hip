@@ -77,6 +77,7 @@ struct Plan {
     int waves = 4;
     std::vector<WinInfo> win;
     std::vector<Tile> tiles;
+    std::vector<int32_t> order;   // launch order of the tiles: estimated heaviest first
     std::vector<int32_t> opt_map;
     std::vector<int32_t> kf_off, pt_off, obs_off;
     size_t lin_lds = 0, upd_lds = 0, chol_lds = 0;
@@ -86,7 +87,7 @@ struct Plan {
     int64_t red_elems = 0;
     int64_t dp_elems = 0;
     // workspace byte offsets
-    size_t o_win, o_tiles, o_opt, o_kfoff, o_ptoff, o_obsoff, o_upload_end;
+    size_t o_win, o_tiles, o_order, o_opt, o_kfoff, o_ptoff, o_obsoff, o_upload_end;
     size_t o_ptstart, o_ctl, o_T, o_X0, o_X1, o_part, o_partr, o_partd, o_partu, o_red, o_redflag, o_dp, o_pf,
         o_stats, o_err, total;
 };
@@ -223,6 +224,20 @@ lba_status build_plan(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, Pl
         pl.max_obs = std::max<int64_t>(pl.max_obs, W.N);
     }
     if (red > INT32_MAX) return set_error(ctx, LBA_ERR_UNSUPPORTED, "batch too large");
+    // launch the tiles heaviest first (estimated observations times a cost growing with
+    // the window's reduced system), so that the light ones fill the end of the launch
+    {
+        std::vector<double> wgt(pl.tiles.size());
+        for (size_t t = 0; t < pl.tiles.size(); ++t) {
+            const Tile &T = pl.tiles[t];
+            const WinInfo &W = pl.win[T.win];
+            const double obs = W.M > 0 ? (double)W.N * (T.p1 - T.p0) / W.M : 0.0;
+            wgt[t] = obs * (W.Kopt + 8);
+        }
+        pl.order.resize(pl.tiles.size());
+        for (size_t t = 0; t < pl.order.size(); ++t) pl.order[t] = (int32_t)t;
+        std::stable_sort(pl.order.begin(), pl.order.end(), [&](int32_t x, int32_t y) { return wgt[x] > wgt[y]; });
+    }
     pl.part_elems = std::max<int64_t>(part, 1);
     pl.partr_elems = std::max<int64_t>(partr, 1);
     pl.red_elems = std::max<int64_t>(red, 1);
@@ -248,6 +263,7 @@ lba_status build_plan(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, Pl
     size_t o = 0;
     pl.o_win = o;    o = align256(o + sizeof(WinInfo) * nw);
     pl.o_tiles = o;  o = align256(o + sizeof(Tile) * std::max<size_t>(pl.tiles.size(), 1));
+    pl.o_order = o;  o = align256(o + sizeof(int32_t) * std::max<size_t>(pl.tiles.size(), 1));
     pl.o_opt = o;    o = align256(o + sizeof(int32_t) * std::max(P->n_kf, 1));
     pl.o_kfoff = o;  o = align256(o + sizeof(int32_t) * (nw + 1));
     pl.o_ptoff = o;  o = align256(o + sizeof(int32_t) * (nw + 1));
@@ -444,7 +460,10 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
     unsigned char *up = static_cast<unsigned char *>(ctx->pinned);
     unsigned char *down = up + pl.o_upload_end;
     memcpy(up + pl.o_win, pl.win.data(), sizeof(WinInfo) * nw);
-    if (!pl.tiles.empty()) memcpy(up + pl.o_tiles, pl.tiles.data(), sizeof(Tile) * pl.tiles.size());
+    if (!pl.tiles.empty()) {
+        memcpy(up + pl.o_tiles, pl.tiles.data(), sizeof(Tile) * pl.tiles.size());
+        memcpy(up + pl.o_order, pl.order.data(), sizeof(int32_t) * pl.order.size());
+    }
     if (P->n_kf > 0) memcpy(up + pl.o_opt, pl.opt_map.data(), sizeof(int32_t) * P->n_kf);
     memcpy(up + pl.o_kfoff, pl.kf_off.data(), sizeof(int32_t) * (nw + 1));
     memcpy(up + pl.o_ptoff, pl.pt_off.data(), sizeof(int32_t) * (nw + 1));
@@ -532,6 +551,7 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
     memset(&la, 0, sizeof(la));
     la.win = d_win;
     la.tiles = d_tiles;
+    la.order = static_cast<const int32_t *>(W_(pl.o_order));
     la.opt_map = d_opt;
     la.pt_start = d_ptstart;
     la.T = d_T;
@@ -569,6 +589,7 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
     memset(&ua, 0, sizeof(ua));
     ua.win = d_win;
     ua.tiles = d_tiles;
+    ua.order = static_cast<const int32_t *>(W_(pl.o_order));
     ua.opt_map = d_opt;
     ua.pt_start = d_ptstart;
     ua.T = d_T;

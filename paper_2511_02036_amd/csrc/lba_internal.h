@@ -74,6 +74,7 @@ struct SolveConsts {
 struct LinArgs {
     const WinInfo *win;
     const Tile *tiles;
+    const int32_t *order;        // launch order: block b processes tile order[b]
     const int32_t *opt_map;      // global kf -> window-local optimisable index or -1
     const int32_t *pt_start;     // global point -> first global observation (n_pt + 1)
     const double *T;             // working poses
@@ -112,6 +113,7 @@ struct CholArgs {
 struct UpdArgs {
     const WinInfo *win;
     const Tile *tiles;
+    const int32_t *order;        // launch order: block b processes tile order[b]
     const int32_t *opt_map;
     const int32_t *pt_start;
     const double *T;
