@@ -63,8 +63,10 @@ hipError_t launch_reduce(const ReduceArgs &a, int n_windows, hipStream_t s) {
 // reads) and factors it redundantly in registers, so no lane-to-lane traffic sits on the
 // serial path; each thread then solves one row of the panel below the block, and after
 // one barrier all threads apply the rank-8 update to the trailing triangle in 4x4
-// register tiles.  The solves reuse the panels: the 8x8 triangular solve is again done
-// redundantly by every thread, followed by a parallel update of the other rows.
+// register tiles.  The forward solve L y = r rides along: every thread also solves the
+// panel's 8 entries of y redundantly, and the thread of each row below subtracts its
+// share.  The backward solve walks the panels from the last, every thread solving the
+// panel's 8 entries from prefetched registers, then all threads updating the rows above.
 // ------------------------------------------------------------------------------------
 #ifndef LBA_CHOL_NB
 #define LBA_CHOL_NB 8
@@ -102,9 +104,8 @@ __device__ __forceinline__ bool diag_block_factor(const double *A, int c0, int n
 #pragma unroll
             for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
             if (!(d > 0.0) || !isfinite(d)) ok = false;
-            const double l = sqrt(d);
-            const double r = 1.0 / l;
-            L[j][j] = l;
+            const double r = rsqrt(d);   // one reciprocal square root on the serial path
+            L[j][j] = d * r;
             rd[j] = r;
 #pragma unroll
             for (int i = j + 1; i < kNB; ++i) {
@@ -153,6 +154,15 @@ __global__ __launch_bounds__(kCholThreads) void k_cholesky(CholArgs a) {
         const int b0 = c0 + nbk;
         double L[kNB][kNB], rd[kNB];
         const bool ok = diag_block_factor(A, c0, nbk, L, rd);
+        // the panel's entries of y (forward solve), redundantly in every thread
+        double yp[kNB];
+#pragma unroll
+        for (int j = 0; j < kNB; ++j) {
+            double v = j < nbk ? y[c0 + j] : 0.0;
+#pragma unroll
+            for (int k = 0; k < j; ++k) v -= L[j][k] * yp[k];
+            yp[j] = v * rd[j];
+        }
         if (!ok) {
             if (tid == 0) s_fail = 1;
         } else {
@@ -168,9 +178,13 @@ __global__ __launch_bounds__(kCholThreads) void k_cholesky(CholArgs a) {
                     for (int k = 0; k < j; ++k) v -= x[k] * L[j][k];
                     x[j] = v * rd[j];
                 }
+                double dy = 0.0;
 #pragma unroll
-                for (int j = 0; j < kNB; ++j)
+                for (int j = 0; j < kNB; ++j) {
                     if (j < nbk) A[packed_lower(r, c0 + j)] = x[j];
+                    dy += x[j] * yp[j];
+                }
+                y[r] -= dy;   // this thread owns row r of y in this phase
             }
             // the factored diagonal block goes to Ld (A's copy is still being read by
             // other threads in this phase)
@@ -194,6 +208,14 @@ __global__ __launch_bounds__(kCholThreads) void k_cholesky(CholArgs a) {
         }
         __syncthreads();
         if (s_fail) break;
+        // the panel's solved entries of y (every thread has read the unsolved ones)
+        if (tid < nbk) {
+            double v = 0.0;
+#pragma unroll
+            for (int jj = 0; jj < kNB; ++jj)
+                if (jj == tid) v = yp[jj];
+            y[c0 + tid] = v;
+        }
         // trailing update A[i][j] -= sum_kk L[i][c0+kk] L[j][c0+kk], b0 <= j <= i < n
         const int m = n - b0;
         const int T4 = (m + 3) / 4;
@@ -230,54 +252,26 @@ __global__ __launch_bounds__(kCholThreads) void k_cholesky(CholArgs a) {
     }
     const int ok = !s_fail;
 
-    // ---- L y = r, then L^T x = y (one barrier per panel) --------------------------------
+    // ---- L^T x = y (y was solved with the factorisation; one barrier per panel) ------
     if (ok) {
-        for (int c0 = 0; c0 < n; c0 += kNB) {
-            const int nbk = min(kNB, n - c0);
-            double yp[kNB];
-#pragma unroll
-            for (int j = 0; j < kNB; ++j) {
-                if (j < nbk) {
-                    double v = y[c0 + j];
-#pragma unroll
-                    for (int k = 0; k < j; ++k) v -= Ld[(c0 + j) * kNB + k] * yp[k];
-                    yp[j] = v * rdiag[c0 + j];
-                } else {
-                    yp[j] = 0.0;
-                }
-            }
-            __syncthreads();   // every thread has read y[c0 .. c0 + nbk)
-            if (tid < nbk) {
-                double v = 0.0;
-#pragma unroll
-                for (int j = 0; j < kNB; ++j)
-                    if (j == tid) v = yp[j];
-                y[c0 + tid] = v;
-            }
-            for (int i = c0 + nbk + tid; i < n; i += nth) {
-                double acc = 0.0;
-#pragma unroll
-                for (int kk = 0; kk < kNB; ++kk)
-                    if (kk < nbk) acc += A[packed_lower(i, c0 + kk)] * yp[kk];
-                y[i] -= acc;
-            }
-            __syncthreads();
-        }
         const int last = n > 0 ? ((n - 1) / kNB) * kNB : 0;
         for (int c0 = last; c0 >= 0 && n > 0; c0 -= kNB) {
             const int nbk = min(kNB, n - c0);
-            double xp[kNB];
+            // the panel's diagonal block and right side, all loads issued before the chain
+            double Lb[kNB][kNB], yb[kNB], rb[kNB], xp[kNB];
+#pragma unroll
+            for (int k = 0; k < kNB; ++k) {
+                yb[k] = k < nbk ? y[c0 + k] : 0.0;
+                rb[k] = k < nbk ? rdiag[c0 + k] : 0.0;
+#pragma unroll
+                for (int j = 0; j < k; ++j) Lb[k][j] = k < nbk ? Ld[(c0 + k) * kNB + j] : 0.0;
+            }
 #pragma unroll
             for (int j = kNB - 1; j >= 0; --j) {
-                if (j < nbk) {
-                    double v = y[c0 + j];
+                double v = yb[j];
 #pragma unroll
-                    for (int k = j + 1; k < kNB; ++k)
-                        if (k < nbk) v -= Ld[(c0 + k) * kNB + j] * xp[k];
-                    xp[j] = v * rdiag[c0 + j];
-                } else {
-                    xp[j] = 0.0;
-                }
+                for (int k = j + 1; k < kNB; ++k) v -= Lb[k][j] * xp[k];
+                xp[j] = v * rb[j];
             }
             __syncthreads();
             if (tid < nbk) {
