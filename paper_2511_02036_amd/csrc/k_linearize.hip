@@ -30,9 +30,6 @@
 // The gradient bp itself is not needed: the gain-ratio denominator uses
 // dp^T bp = dp^T r + sum_j q_j^T V_j^-1 bl_j (q_j = sum_a W_a^T dp), whose point part
 // the update kernel forms.
-//
-// INIT mode computes only what the damping initialisation needs: the cost, the diagonal
-// of Hpp per camera (in the r slots) and the largest point-block diagonal.
 #include "lba_internal.h"
 
 namespace lba {
@@ -41,7 +38,6 @@ constexpr int kNT = kLinThreads;           // 512
 constexpr int kGroups = kLinThreads / 36;  // 14 groups of 36 threads, one block entry each
 constexpr int kSlots = 34;                 // blocks per group (14 * 34 >= 465)
 constexpr int kMaxBlocks = 465;            // Kopt <= 30
-constexpr int kMaxN = 180;
 constexpr int kMaxOpt = 30;
 
 template <typename Real>
@@ -60,7 +56,6 @@ struct LinSmem {
     Real *Z;         // CO x 18
     double *hs;      // CO x 9    FP64 Hll_a (6) and bl_a (3) for the point sums
     double *dacc;    // kMaxOpt x 27: per camera, sum of D_a (lower triangle, 21) and r_a (6)
-    double *hd;      // kMaxN: INIT only, diagonal of Hpp of the chunk
     unsigned *pairs; // PCAP
     Real *prod;      // PB x PS: signed 6 x 6 contribution of each pair of the current batch
     int *cnt;        // kMaxBlocks + 1 (then list offsets)
@@ -131,11 +126,10 @@ __host__ __device__ inline size_t lin_carve(unsigned char *base, int K, LinSmem<
     void *oka = take(sizeof(int) * C::CO);
     void *scan = take(sizeof(int) * 16);
     void *red = take(sizeof(double) * 32);
-    void *hd = take(sizeof(double) * kMaxN);
     if (s) {
         s->T = (double *)T; s->opt = (int *)opt; s->Z = (Real *)Z; s->hs = (double *)hs; s->dacc = (double *)dacc;
         s->pairs = (unsigned *)pairs; s->prod = (Real *)prod; s->cnt = (int *)cnt; s->cur = (int *)cur; s->touch = (unsigned long long *)touch; s->oka = (int *)oka;
-        s->scan = (int *)scan; s->red = (double *)red; s->hd = (double *)hd;
+        s->scan = (int *)scan; s->red = (double *)red;
     }
     return o;
 }
@@ -181,7 +175,7 @@ __device__ __forceinline__ int block_inclusive_scan(int v, int *scan, int tid) {
     return x + add;
 }
 
-template <typename Real, typename ZT, bool INIT>
+template <typename Real, typename ZT>
 __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
     using C = LinCfg<Real>;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -189,7 +183,7 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
     const Tile tile = a.tiles[t];
     const WinInfo W = a.win[tile.win];
     const Ctl ctl = a.ctl[tile.win];
-    if (!INIT && !ctl.running) return;
+    if (!ctl.running) return;
     const int K = W.K, n = W.n, E = W.E, Kopt = W.Kopt;
     const int nblk = Kopt * (Kopt + 1) / 2;
     LinSmem<Real> sm;
@@ -208,7 +202,7 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
     // blocks B = g + 14 k (kA <= kB).  In a diagonal block the entries j <= i are S, the six
     // upper positions 1 2 3 4 5 8 accumulate r of that camera, the rest are unused.
     const int grp = tid / 36, qe = tid - 36 * grp;
-    const int nent = INIT ? 0 : nblk;
+    const int nent = nblk;
     double acc[kSlots];
 #pragma unroll
     for (int k = 0; k < kSlots; ++k) acc[k] = 0.0;
@@ -224,19 +218,16 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             else if (diag && rpos) m_r |= 1ull << k;
         }
     }
-    double racc = 0.0;   // INIT: Hpp diagonal entry tid
-    if (!INIT)
-        for (int i = tid; i < Kopt * 27; i += kNT) sm.dacc[i] = 0.0;
+    for (int i = tid; i < Kopt * 27; i += kNT) sm.dacc[i] = 0.0;
     __syncthreads();
 
     const CamParams cam = a.c.cam;
-    double Facc = 0.0, mdiag = 0.0;
+    double Facc = 0.0;
     int fail = 0;
 
     for (int p = tile.p0; p < tile.p1;) {
         // ---- chunk of whole points: <= CO observations and <= PCAP pairs ------------
-        if (!INIT)
-            for (int i = tid; i < Kopt * 8; i += kNT) cm[i] = 0ull;
+        for (int i = tid; i < Kopt * 8; i += kNT) cm[i] = 0ull;
         const int base = a.pt_start[p];
         const int cand = p + tid;
         int mpairs = 0, inrange = 0, obs_incl = 0;
@@ -311,7 +302,7 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             for (int i = 0; i < 3; ++i) sm.hs[tid * 9 + 6 + i] = bl[i];
             if (!act) ka = -1;
             sm.oka[tid] = ka;
-            if (!INIT && ka >= 0) {   // the point in its camera's mask; a second hit is a duplicate
+            if (ka >= 0) {   // the point in its camera's mask; a second hit is a duplicate
                 const unsigned long long bit = 1ull << (pl & 63);
                 dup = (__hip_atomic_fetch_or(&cm[ka * 8 + (pl >> 6)], bit, __ATOMIC_RELAXED,
                                              __HIP_MEMORY_SCOPE_WORKGROUP) & bit) != 0;
@@ -331,36 +322,7 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
                 for (int i = 0; i < 3; ++i) bs[i] += sm.hs[m * 9 + 6 + i];
             }
         }
-        if (INIT && tid < n) sm.hd[tid] = 0.0;
         __syncthreads();
-        if (INIT) {
-            if (has && tid == s0) mdiag = fmax(mdiag, fmax(V[0], fmax(V[3], V[5])));
-            if (ka >= 0) {
-                const double *T = sm.T + kl * 12;
-                double xc, yc, zc, eu, ev, er;
-                residual(cam, T, X0, X1, X2, zu, zv, zr, stereo, xc, yc, zc, eu, ev, er);
-                ObsBlocks<Real> Bk;
-                obs_blocks<Real>(cam, T, xc, yc, zc, eu, ev, er, stereo, (Real)omd, Bk);
-                Real H[36], bpa[6];
-                pose_terms<Real>(Bk, H, bpa);
-                // diagonal of Hpp_a into the block's LDS sums (entry order rotated by thread)
-                const int rot = tid % 6;
-                for (int e = 0; e < 6; ++e) {
-                    int i = e + rot;
-                    i -= i >= 6 ? 6 : 0;
-                    double v = 0.0;
-#pragma unroll
-                    for (int c = 0; c < 6; ++c)
-                        if (c == i) v = (double)H[c * 7];
-                    lds_add(&sm.hd[ka * 6 + i], v);
-                }
-            }
-            __syncthreads();
-            if (tid < n) racc += sm.hd[tid];
-            __syncthreads();
-            p = q;
-            continue;
-        }
         double Li[6] = {0, 0, 0, 0, 0, 0};
         double t0 = 0, t1 = 0, t2 = 0;
         if (has) {
@@ -369,7 +331,7 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             V[5] += lambda;
             if (!chol3_inv<double>(V, Li)) fail = 1;
             lmul<double>(Li, bs[0], bs[1], bs[2], t0, t1, t2);
-            if (!INIT && tid == s0) {   // the point's factor, for this step's back-substitution
+            if (tid == s0) {   // the point's factor, for this step's back-substitution
                 double *f = a.pf + 12 * (int64_t)(p + pl);
 #pragma unroll
                 for (int i = 0; i < 6; ++i) f[i] = Li[i];
@@ -538,7 +500,7 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
     }
 
     // ---- write-out: owned rows of S, r, and the tile's scalars ----------------------
-    if (!INIT) {
+    {
         double *part = a.part + W.part_off + (int64_t)(t - W.tile0) * W.part_stride;
         double *pr = a.partr + W.partr_off + (int64_t)(t - W.tile0) * n;
 #pragma unroll
@@ -558,15 +520,12 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             const int ra = 6 * kA + ie, col = 6 * kB + je;
             part[ra >= col ? packed_lower(ra, col) : packed_lower(col, ra)] = v;
         }
-    } else if (tid < n) {
-        a.partr[W.partr_off + (int64_t)(t - W.tile0) * n + tid] = racc;
     }
     Facc = wave_sum(Facc);
-    mdiag = wave_max(mdiag);
     const int anyfail = __syncthreads_or(fail);
     if ((tid & 63) == 0) {
         sm.red[(tid >> 6) * 2] = Facc;
-        sm.red[(tid >> 6) * 2 + 1] = mdiag;
+        sm.red[(tid >> 6) * 2 + 1] = 0.0;
     }
     __syncthreads();
     if (tid == 0) {
@@ -583,20 +542,17 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
     (void)E;
 }
 
-hipError_t launch_linearize(const LinArgs &a, int ntiles, size_t lds, bool init, bool mixed,
-                            hipStream_t s) {
+hipError_t launch_linearize(const LinArgs &a, int ntiles, size_t lds, bool mixed, hipStream_t s) {
     if (ntiles <= 0) return hipSuccess;
     dim3 grid(ntiles), block(kNT);
     const bool zf = a.obs.z_f32 != 0;
-#define LBA_LAUNCH(R, Z, I) hipLaunchKernelGGL((k_linearize<R, Z, I>), grid, block, lds, s, a)
     if (mixed) {
-        if (zf) { if (init) LBA_LAUNCH(float, float, true); else LBA_LAUNCH(float, float, false); }
-        else { if (init) LBA_LAUNCH(float, double, true); else LBA_LAUNCH(float, double, false); }
+        if (zf) hipLaunchKernelGGL((k_linearize<float, float>), grid, block, lds, s, a);
+        else hipLaunchKernelGGL((k_linearize<float, double>), grid, block, lds, s, a);
     } else {
-        if (zf) { if (init) LBA_LAUNCH(double, float, true); else LBA_LAUNCH(double, float, false); }
-        else { if (init) LBA_LAUNCH(double, double, true); else LBA_LAUNCH(double, double, false); }
+        if (zf) hipLaunchKernelGGL((k_linearize<double, float>), grid, block, lds, s, a);
+        else hipLaunchKernelGGL((k_linearize<double, double>), grid, block, lds, s, a);
     }
-#undef LBA_LAUNCH
     return hipGetLastError();
 }
 

@@ -80,7 +80,7 @@ struct Plan {
     std::vector<int32_t> order;   // launch order of the tiles: estimated heaviest first
     std::vector<int32_t> opt_map;
     std::vector<int32_t> kf_off, pt_off, obs_off;
-    size_t lin_lds = 0, upd_lds = 0, chol_lds = 0;
+    size_t lin_lds = 0, upd_lds = 0, chol_lds = 0, init_lds = 0;
     int max_En = 0;
     int64_t part_elems = 0;
     int64_t partr_elems = 0;
@@ -254,6 +254,7 @@ lba_status build_plan(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, Pl
     if (!pl.waves || lin_lds_bytes(maxK, maxn, 0, pl.mixed) > (size_t)ctx->max_lds)
         return set_error(ctx, LBA_ERR_UNSUPPORTED, "window of %d keyframes does not fit in LDS", maxK);
     pl.lin_lds = lin_lds_bytes(maxK, maxn, 0, pl.mixed);
+    pl.init_lds = init_lds_bytes(maxK, maxn);
     pl.upd_lds = upd_lds_bytes(maxK, maxn, pl.waves, pl.mixed);
     pl.chol_lds = chol_lds_bytes(maxn);
     if (pl.chol_lds > (size_t)ctx->max_lds)
@@ -637,8 +638,7 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
         ua.robust = robust;
         da.round = round;
         ia.round = round;
-        HIPCHK(timed(ctx, LBA_KCLASS_LINEARIZE_INIT, s,
-                     [&] { return launch_linearize(la, ntiles, pl.lin_lds, true, pl.mixed, s); }));
+        HIPCHK(timed(ctx, LBA_KCLASS_LINEARIZE_INIT, s, [&] { return launch_init(la, ntiles, pl.init_lds, s); }));
         HIPCHK(timed(ctx, LBA_KCLASS_INIT_REDUCE, s, [&] { return launch_init_reduce(ia, nw, s); }));
         int steps_done = 0;
         int nsteps = iters;
@@ -647,7 +647,7 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
         auto step = [&](hipStream_t q) -> hipError_t {
             hipError_t e;
             if ((e = timed(ctx, LBA_KCLASS_LINEARIZE, q,
-                           [&] { return launch_linearize(la, ntiles, pl.lin_lds, false, pl.mixed, q); })) != hipSuccess)
+                           [&] { return launch_linearize(la, ntiles, pl.lin_lds, pl.mixed, q); })) != hipSuccess)
                 return e;
             if ((e = timed(ctx, LBA_KCLASS_REDUCE, q, [&] { return launch_reduce(ra, nw, q); })) != hipSuccess) return e;
             if ((e = timed(ctx, LBA_KCLASS_CHOLESKY, q, [&] { return launch_cholesky(ca, nw, pl.chol_lds, q); })) !=

@@ -204,9 +204,9 @@ struct CostArgs {
 // ------------------------------------------------------------------------------------
 // launchers (one per translation unit that owns the kernel)
 // ------------------------------------------------------------------------------------
-hipError_t launch_linearize(const LinArgs &a, int ntiles, size_t lds, bool init, bool mixed,
-                            hipStream_t s);
+hipError_t launch_linearize(const LinArgs &a, int ntiles, size_t lds, bool mixed, hipStream_t s);
 hipError_t launch_update(const UpdArgs &a, int ntiles, size_t lds, bool mixed, hipStream_t s);
+hipError_t launch_init(const LinArgs &a, int ntiles, size_t lds, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs &a, int n_windows, hipStream_t s);
 hipError_t launch_cholesky(const CholArgs &a, int n_windows, size_t lds, hipStream_t s);
 hipError_t launch_decide(const DecideArgs &a, int n_windows, hipStream_t s);
@@ -223,6 +223,7 @@ size_t lin_lds_bytes(int K, int n, int waves, bool mixed);
 size_t upd_lds_bytes(int K, int n, int waves, bool mixed);
 size_t chol_lds_bytes(int n);
 size_t cost_lds_bytes(int K, bool backward);
+size_t init_lds_bytes(int K, int n);
 
 #if defined(__HIPCC__)
 // ------------------------------------------------------------------------------------

@@ -15,7 +15,7 @@ HIPCC = "/opt/rocm/bin/hipcc"
 
 
 @pytest.mark.skipif(not os.path.exists(HIPCC), reason="hipcc not installed")
-@pytest.mark.parametrize("src", ["k_linearize.hip", "k_update.hip", "k_cost.hip", "k_solve.hip"])
+@pytest.mark.parametrize("src", ["k_linearize.hip", "k_update.hip", "k_cost.hip", "k_solve.hip", "k_init.hip"])
 def test_hot_kernels_use_no_scratch(src, tmp_path):
     cmd = [HIPCC, "-O3", "-std=c++17", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
            "-packed-fp32-ops", "-I", os.path.join(ROOT, "include"), "-I", CSRC, "--cuda-device-only", "-c",
