@@ -213,6 +213,7 @@ typedef enum {
     LBA_KCLASS_FINALIZE,
     LBA_KCLASS_COST_FORWARD,     /* robust-cost layer, forward */
     LBA_KCLASS_COST_BACKWARD,    /* robust-cost layer, backward */
+    LBA_KCLASS_ORDER,            /* once per solve: point order of the linearisation */
     LBA_KCLASS_COUNT
 } lba_kernel_class;
 

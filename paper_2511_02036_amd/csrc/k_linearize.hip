@@ -1,6 +1,8 @@
 // Linearisation + Schur complement kernel (owner-computes).
 //
-// One 512-thread block per tile of consecutive points of one window.  The block's share
+// One 512-thread block per tile of one window's points, taken in the window's
+// linearisation order (points sorted by the keyframes that observe them, so that a
+// chunk's points share keyframes; the order is built once per solve).  The block's share
 // of the reduced camera system
 //     S = Hpp + lambda I - sum_j sum_{a,b in obs(j)} W_a V_j^-1 W_b^T,
 //     r = bp - sum_j sum_{a in obs(j)} W_a V_j^-1 bl_j,
@@ -18,11 +20,13 @@
 //      two camera masks, and a pair's place is the number of the block's points before
 //      its own (a chunk with two observations of one point on one camera falls back to
 //      LDS integer atomics);
-//   4. in batches of PB pairs, one thread per pair writes -Z_a Z_b^T (lower triangle of
-//      Z_a Z_b^T + Z_b Z_a^T for two observations on one camera) to LDS in list order;
-//      14 groups of 36 threads each own one entry of every 14th camera block and add up
-//      the contiguous run of their block in FP64 registers (no two threads add into the
-//      same entry, no atomics touch S).
+//   4. each block's run of the list is cut into pieces of at most kPiece pairs (4 in
+//      FP32, 1 in FP64); in
+//      batches of PB pieces, two threads per piece (three rows each) write the piece's
+//      sum of -Z_a Z_b^T (lower triangle of Z_a Z_b^T + Z_b Z_a^T for two observations on
+//      one camera) to LDS in list order; 14 groups of 36 threads each own one entry of
+//      every 14th camera block and add up the contiguous run of their block's pieces in
+//      FP64 registers (no two threads add into the same entry, no atomics touch S).
 // At the end of the tile each owner writes its entry, plus the per-camera sums on the
 // diagonal blocks, to the tile's partial system; a separate kernel sums the partials of
 // a window in a fixed order (no global atomics).  The per-camera sums of step 2 are
@@ -44,9 +48,14 @@ template <typename Real>
 struct LinCfg {
     static constexpr int CO = sizeof(Real) == 4 ? 512 : 256;   // observations per chunk
     static constexpr int PCAP = sizeof(Real) == 4 ? 3072 : 2080;   // pairs per chunk (>= 64*65/2)
-    static constexpr int PB = sizeof(Real) == 4 ? 512 : 256;   // pair products per batch
+    static constexpr int PB = 256;                             // pieces per batch
+    // pairs per piece: FP32 sums up to four in registers; FP64, whose owner registers
+    // leave no room for 18 more doubles, takes one pair per piece
+    static constexpr int kPiece = sizeof(Real) == 4 ? 4 : 1;
     static constexpr int PS = 37;                              // product row stride (odd)
     static constexpr int RPT = 6 * PB / kNT;                   // product rows per thread
+    static_assert(RPT == 3, "two threads per piece");
+    static_assert(PCAP < 65536, "packed scan of pair and piece counts");
 };
 
 template <typename Real>
@@ -56,9 +65,10 @@ struct LinSmem {
     Real *Z;         // CO x 18
     double *hs;      // CO x 9    FP64 Hll_a (6) and bl_a (3) for the point sums
     double *dacc;    // kMaxOpt x 27: per camera, sum of D_a (lower triangle, 21) and r_a (6)
-    unsigned *pairs; // PCAP
-    Real *prod;      // PB x PS: signed 6 x 6 contribution of each pair of the current batch
-    int *cnt;        // kMaxBlocks + 1 (then list offsets)
+    unsigned *pairs; // PCAP pairs, then PCAP + 1 piece starts (list positions)
+    Real *prod;      // PB x PS: signed 6 x 6 sum of each piece of the current batch
+    int *cnt;        // kMaxBlocks + 1 pair counts (then list offsets), then kMaxBlocks + 1
+                     // piece offsets
     int *cur;        // kMaxBlocks
     int *oka;        // CO: optimisable camera of the chunk observation (-1: none)
     int *scan;       // 16: per-wavefront totals
@@ -67,36 +77,64 @@ struct LinSmem {
     double *red;     // 16 x 2
 };
 
-// rows R0 .. R0 + NR - 1 of the signed 6 x 6 product of one pair (la, lb, flag fl)
-template <int R0, int NR, typename Real>
-__device__ __forceinline__ void pair_product(const LinSmem<Real> &sm, int la, int lb, int fl, Real *out) {
-    // rows i of Z_a (and Z_b) stay in registers; rows j are streamed from LDS
-    const Real *za = sm.Z + la * 18, *zb = sm.Z + lb * 18;
-    Real ai[3 * NR], bi[3 * NR];
+// rows R0 .. R0 + 2 of the signed 6 x 6 sum over the pairs [r0, r1) of one piece (all
+// of one camera block, so all with the same flag).  Pieces of several pairs sum in
+// registers; one-pair pieces (FP64) write the product straight to their LDS row.
+template <int R0, typename Real>
+__device__ __forceinline__ void piece_product(const LinSmem<Real> &sm, int r0, int r1, int fl, Real *out) {
+    constexpr bool kRegs = LinCfg<Real>::kPiece > 1;
+    Real acc[kRegs ? 18 : 1];
 #pragma unroll
-    for (int c = 0; c < 3 * NR; ++c) {
-        ai[c] = za[R0 * 3 + c];
-        bi[c] = fl == 2 ? zb[R0 * 3 + c] : (Real)0;
+    for (int c = 0; c < (kRegs ? 18 : 1); ++c) acc[c] = (Real)0;
+    for (int r = r0; r < r1; ++r) {
+        const unsigned e = sm.pairs[r];
+        const Real *za = sm.Z + (e & 1023) * 18, *zb = sm.Z + ((e >> 10) & 1023) * 18;
+        const bool first = !kRegs || r == r0;   // one-pair pieces write, never add
+        Real ai[9];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) ai[c] = za[R0 * 3 + c];
+        if (fl == 0) {   // Z_a Z_b^T, camera of a before camera of b
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                const Real b0 = zb[j * 3], b1 = zb[j * 3 + 1], b2 = zb[j * 3 + 2];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    const Real v = ai[i * 3] * b0 + ai[i * 3 + 1] * b1 + ai[i * 3 + 2] * b2;
+                    if constexpr (kRegs) acc[i * 6 + j] += v;
+                    else {
+                        Real *o = out + (R0 + i) * 6 + j;
+                        *o = first ? -v : *o - v;
+                    }
+                }
+            }
+        } else {         // one camera twice: Z_a Z_b^T + Z_b Z_a^T, lower triangle
+            Real bi[9];
+#pragma unroll
+            for (int c = 0; c < 9; ++c) bi[c] = zb[R0 * 3 + c];
+#pragma unroll
+            for (int j = 0; j < R0 + 3; ++j) {
+                const Real b0 = zb[j * 3], b1 = zb[j * 3 + 1], b2 = zb[j * 3 + 2];
+                const Real a0 = za[j * 3], a1 = za[j * 3 + 1], a2 = za[j * 3 + 2];
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+                    if (j <= R0 + i) {
+                        const Real v = ai[i * 3] * b0 + ai[i * 3 + 1] * b1 + ai[i * 3 + 2] * b2 + bi[i * 3] * a0 +
+                                       bi[i * 3 + 1] * a1 + bi[i * 3 + 2] * a2;
+                        if constexpr (kRegs) acc[i * 6 + j] += v;
+                        else {
+                            Real *o = out + (R0 + i) * 6 + j;
+                            *o = first ? -v : *o - v;
+                        }
+                    }
+            }
+        }
     }
-    if (fl == 0) {   // -Z_a Z_b^T, camera of a before camera of b
+    if constexpr (kRegs) {
 #pragma unroll
-        for (int j = 0; j < 6; ++j) {
-            const Real b0 = zb[j * 3], b1 = zb[j * 3 + 1], b2 = zb[j * 3 + 2];
+        for (int i = 0; i < 3; ++i)
 #pragma unroll
-            for (int i = 0; i < NR; ++i)
-                out[(R0 + i) * 6 + j] = -(ai[i * 3] * b0 + ai[i * 3 + 1] * b1 + ai[i * 3 + 2] * b2);
-        }
-    } else {         // one camera twice: -(Z_a Z_b^T + Z_b Z_a^T), lower triangle
-#pragma unroll
-        for (int j = 0; j < R0 + NR; ++j) {
-            const Real b0 = zb[j * 3], b1 = zb[j * 3 + 1], b2 = zb[j * 3 + 2];
-            const Real a0 = za[j * 3], a1 = za[j * 3 + 1], a2 = za[j * 3 + 2];
-#pragma unroll
-            for (int i = 0; i < NR; ++i)
-                if (j <= R0 + i)
-                    out[(R0 + i) * 6 + j] = -(ai[i * 3] * b0 + ai[i * 3 + 1] * b1 + ai[i * 3 + 2] * b2 +
-                                              bi[i * 3] * a0 + bi[i * 3 + 1] * a1 + bi[i * 3 + 2] * a2);
-        }
+            for (int j = 0; j < 6; ++j)
+                if (fl == 0 || j <= R0 + i) out[(R0 + i) * 6 + j] = -acc[i * 6 + j];
     }
 }
 
@@ -110,17 +148,17 @@ __host__ __device__ inline size_t lin_carve(unsigned char *base, int K, LinSmem<
     void *T = take(sizeof(double) * 12 * K);
     void *opt = take(sizeof(int) * K);
     void *Z = take(sizeof(Real) * C::CO * 18);
-    // the point-sum staging of phases 1-2 and the pair products of phase 4 share space
-    static_assert(sizeof(double) * C::CO * 9 <= sizeof(Real) * C::PB * C::PS, "staging overlay");
-    void *prod = take(sizeof(Real) * C::PB * C::PS);
+    // the staging of phases 1-2 (point-sum terms, then the chunk's point positions (512 x
+    // 3), observation ranges (513), first observations and indices of its points (512
+    // each) and the point of each observation slot (CO), see the kernel) and the piece
+    // products of phase 4 share space
+    constexpr size_t kStage = sizeof(double) * (C::CO * 9 + kNT * 3) + sizeof(int) * (kNT + 1 + 2 * kNT + C::CO);
+    constexpr size_t kProd = sizeof(Real) * C::PB * C::PS;
+    void *prod = take(kStage > kProd ? kStage : kProd);
     void *hs = prod;
-    // ... and so do, after it, the chunk's point positions (512 x 3) and observation
-    // ranges (513), see the kernel
-    static_assert(sizeof(double) * (C::CO * 9 + kNT * 3) + sizeof(int) * (kNT + 1) <=
-                      sizeof(Real) * C::PB * C::PS, "staging overlay");
     void *dacc = take(sizeof(double) * kMaxOpt * 27);
-    void *pairs = take(sizeof(unsigned) * C::PCAP);
-    void *cnt = take(sizeof(int) * (kMaxBlocks + 1));
+    void *pairs = take(sizeof(unsigned) * (2 * C::PCAP + 1));
+    void *cnt = take(sizeof(int) * 2 * (kMaxBlocks + 1));
     void *cur = take(sizeof(int) * kMaxBlocks);
     void *touch = take(sizeof(unsigned long long) * (2 * kGroups + kMaxOpt * 8));
     void *oka = take(sizeof(int) * C::CO);
@@ -154,6 +192,28 @@ __device__ __forceinline__ int block_row(int B, int Kopt) {
     return ka;
 }
 
+// inclusive scan of one 64-bit value per thread over the block (512 threads)
+__device__ __forceinline__ long long block_inclusive_scan64(long long v, int *scan, int tid) {
+    const int lane = tid & 63, wave = tid >> 6;
+    long long x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const long long y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    long long *sc = reinterpret_cast<long long *>(scan);
+    if (lane == 63) sc[wave] = x;
+    __syncthreads();
+    long long add = 0;
+#pragma unroll
+    for (int w = 0; w < kNT / 64; ++w) {
+        const long long u = sc[w];
+        add += w < wave ? u : 0;
+    }
+    __syncthreads();
+    return x + add;
+}
+
 // inclusive scan of one int per thread over the block (512 threads)
 __device__ __forceinline__ int block_inclusive_scan(int v, int *scan, int tid) {
     const int lane = tid & 63, wave = tid >> 6;
@@ -178,6 +238,8 @@ __device__ __forceinline__ int block_inclusive_scan(int v, int *scan, int tid) {
 template <typename Real, typename ZT>
 __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
     using C = LinCfg<Real>;
+    // the mixed form takes the points in keyframe order; FP64 in index order
+    constexpr bool kSorted = sizeof(Real) == 4;
     extern __shared__ __align__(16) unsigned char smem[];
     const int t = a.order[blockIdx.x];
     const Tile tile = a.tiles[t];
@@ -191,6 +253,11 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
     unsigned long long *const cm = sm.touch + 2 * kGroups;
     double *const xs = sm.hs + C::CO * 9;               // chunk point positions
     int *const pst = reinterpret_cast<int *>(xs + 3 * kNT);   // chunk-local observation starts
+    int *const gst = pst + kNT + 1;                     // first global observation of each point
+    int *const pid = gst + kNT;                         // global index of each point
+    int *const seg = pid + kNT;                         // chunk point of each observation slot
+    int *const pco = sm.cnt + kMaxBlocks + 1;           // piece offsets per block
+    unsigned *const pcs = sm.pairs + C::PCAP;           // first list position of each piece
     const double lambda = ctl.lambda;
     const double *Xs = ctl.cur ? a.X1 : a.X0;
     const int tid = threadIdx.x;
@@ -226,60 +293,86 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
     int fail = 0;
 
     for (int p = tile.p0; p < tile.p1;) {
+        // The thread index is re-derived per chunk behind an empty asm statement, so the
+        // compiler recomputes the LDS addresses built from it inside the chunk instead of
+        // keeping them all live across the loop (which overflows the FP64 register budget).
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
         // ---- chunk of whole points: <= CO observations and <= PCAP pairs ------------
         for (int i = tid; i < Kopt * 8; i += kNT) cm[i] = 0ull;
-        const int base = a.pt_start[p];
         const int cand = p + tid;
-        int mpairs = 0, inrange = 0, obs_incl = 0;
+        int P = 0, ps = 0, m = 0, inrange = 0;
         if (cand < tile.p1) {
-            const int e = a.pt_start[cand + 1];
-            const int m = e - a.pt_start[cand];
-            mpairs = m * (m + 1) / 2;
-            obs_incl = e - base;
+            const int4 pi = a.pinfo[cand];
+            P = pi.x;
+            ps = pi.y;
+            m = pi.z;
             inrange = 1;
         }
-        const int pincl = block_inclusive_scan(mpairs, sm.scan, tid);
+        // observations (high word) and pair slots (low word) up to and including this point
+        const long long incl =
+            block_inclusive_scan64(((long long)m << 32) | (long long)(m * (m + 1) / 2), sm.scan, tid);
+        const int obs_incl = (int)(incl >> 32), pincl = (int)(incl & 0xffffffffll);
         const int ok = inrange && obs_incl <= C::CO && pincl <= C::PCAP;
         const int q = p + __syncthreads_count(ok);
         if (q == p) {   // one point exceeds a chunk: not solvable here
             fail = 1;
             break;
         }
-        // the chunk's point ranges and positions go to LDS (coalesced, and independent of
-        // the observation loads below, so both are in flight together)
+        // the chunk's point ranges, positions and observation slots go to LDS
         const int np = q - p;
         if (tid < np) {
             pst[tid + 1] = obs_incl;
-            xs[3 * tid] = Xs[3 * (int64_t)cand];
-            xs[3 * tid + 1] = Xs[3 * (int64_t)cand + 1];
-            xs[3 * tid + 2] = Xs[3 * (int64_t)cand + 2];
+            gst[tid] = ps;
+            pid[tid] = P;
+            if (kSorted)
+                for (int i = obs_incl - m; i < obs_incl; ++i) seg[i] = tid;
+            xs[3 * tid] = Xs[3 * (int64_t)P];
+            xs[3 * tid + 1] = Xs[3 * (int64_t)P + 1];
+            xs[3 * tid + 2] = Xs[3 * (int64_t)P + 2];
         }
         if (tid == 0) pst[0] = 0;
-        const int o = base + tid;
-        const bool inb = o < a.obs.n_obs;
-        int jl = 0, kl = 0, stereo = 0, oct = 0;
+        int pl = 0, kl = 0, stereo = 0, oct = 0;
         bool act = false;
         double zu = 0, zv = 0, zr = 0;
-        if (inb) {
-            jl = a.obs.pt[o];
-            kl = a.obs.kf[o];
-            act = !a.mask || !a.mask[o];
-            stereo = a.obs.type[o];
-            oct = a.obs.oct[o];
-            load_z<ZT>(a.obs, o, zu, zv, zr);
+        bool has;
+        if (kSorted) {   // observation slot tid: observation tid - pst[pl] of chunk point pl
+            __syncthreads();
+            has = tid < pst[np];
+            if (has) {
+                pl = seg[tid];
+                const int o = gst[pl] + tid - pst[pl];
+                kl = a.obs.kf[o];
+                act = !a.mask || !a.mask[o];
+                stereo = a.obs.type[o];
+                oct = a.obs.oct[o];
+                load_z<ZT>(a.obs, o, zu, zv, zr);
+            }
+        } else {         // index order: the chunk's observations are contiguous, and their
+                         // loads are in flight together with the point loads above
+            const int o = a.pinfo[p].y + tid;
+            int jl = 0;
+            const bool inb = o < a.obs.n_obs;
+            if (inb) {
+                jl = a.obs.pt[o];
+                kl = a.obs.kf[o];
+                act = !a.mask || !a.mask[o];
+                stereo = a.obs.type[o];
+                oct = a.obs.oct[o];
+                load_z<ZT>(a.obs, o, zu, zv, zr);
+            }
+            __syncthreads();
+            has = tid < pst[np];
+            pl = W.pt0 + jl - p;
         }
-        __syncthreads();
-        const int nob = pst[np];
-        const bool has = tid < nob;
 
         // ---- 1. per-observation terms -------------------------------------------------
         // (only the raw observation stays in registers across the point-sum barrier; the
         //  factored blocks are recomputed from it in phase 2)
-        int s0 = 0, s1 = 0, ka = -1, pl = 0, dup = 0;
+        int s0 = 0, s1 = 0, ka = -1, dup = 0;
         double X0 = 0, X1 = 0, X2 = 0, omd = 0.0;
         double rho = 0.0;
         if (has) {
-            pl = W.pt0 + jl - p;
             s0 = pst[pl];
             s1 = pst[pl + 1];
             ka = sm.opt[kl];
@@ -332,7 +425,7 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             if (!chol3_inv<double>(V, Li)) fail = 1;
             lmul<double>(Li, bs[0], bs[1], bs[2], t0, t1, t2);
             if (tid == s0) {   // the point's factor, for this step's back-substitution
-                double *f = a.pf + 12 * (int64_t)(p + pl);
+                double *f = a.pf + 12 * (int64_t)pid[pl];
 #pragma unroll
                 for (int i = 0; i < 6; ++i) f[i] = Li[i];
                 f[6] = t0; f[7] = t1; f[8] = t2;
@@ -415,18 +508,26 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             }
         }
         __syncthreads();
-        {
-            const int v = tid < nblk ? sm.cnt[tid] : 0;
+        {   // pair offsets (low half) and piece offsets (high half) in one scan
+            const int c = tid < nblk ? sm.cnt[tid] : 0;
+            const int v = c | (((c + C::kPiece - 1) / C::kPiece) << 16);
             const int incl = block_inclusive_scan(v, sm.scan, tid);
-            if (tid < nblk) sm.cnt[tid] = incl - v;   // exclusive offsets
-            if (tid == nblk - 1) sm.cnt[nblk] = incl;
+            if (tid < nblk) {
+                sm.cnt[tid] = (incl - v) & 0xffff;
+                pco[tid] = (incl - v) >> 16;
+            }
+            if (tid == nblk - 1) {
+                sm.cnt[nblk] = incl & 0xffff;
+                pco[nblk] = incl >> 16;
+                if (C::kPiece > 1) pcs[incl >> 16] = (unsigned)(incl & 0xffff);
+            }
         }
         __syncthreads();
         if (ka >= 0) {
             const int pw = pl >> 6;
             const unsigned long long below = (1ull << (pl & 63)) - 1ull;
             for (int b0 = tid + 1; b0 < s1; b0 += 4) {   // partners four at a time
-                int kb[4], B[4], pos[4];
+                int kb[4], B[4], rk[4];   // rk: place within the block's run
 #pragma unroll
                 for (int u = 0; u < 4; ++u) kb[u] = b0 + u < s1 ? sm.oka[b0 + u] : -1;
 #pragma unroll
@@ -435,11 +536,11 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
                     B[u] = block_id(lo, hi, Kopt);
                     if (kb[u] < 0) continue;
                     if (anydup) {
-                        pos[u] = sm.cnt[B[u]] + atomicAdd(&sm.cur[B[u]], 1);
+                        rk[u] = atomicAdd(&sm.cur[B[u]], 1);
                     } else {
                         int r = __popcll(cm[lo * 8 + pw] & cm[hi * 8 + pw] & below);
                         for (int w = 0; w < pw; ++w) r += __popcll(cm[lo * 8 + w] & cm[hi * 8 + w]);
-                        pos[u] = sm.cnt[B[u]] + r;
+                        rk[u] = r;
                     }
                 }
 #pragma unroll
@@ -450,32 +551,36 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
                     // of one point on the same camera
                     const int first = ka <= kb[u] ? tid : b, second = ka <= kb[u] ? b : tid;
                     const unsigned fl = ka == kb[u] ? 2u : 0u;
-                    sm.pairs[pos[u]] = (unsigned)first | ((unsigned)second << 10) | (fl << 20);
+                    const int pos = sm.cnt[B[u]] + rk[u];
+                    sm.pairs[pos] = (unsigned)first | ((unsigned)second << 10) | (fl << 20);
+                    if (C::kPiece > 1 && rk[u] % C::kPiece == 0) pcs[pco[B[u]] + rk[u] / C::kPiece] = (unsigned)pos;
                 }
             }
         }
         __syncthreads();
 
-        // ---- 4. pair products, PB at a time, then each owner sums its rows ---------------
-        const int npairs = nblk > 0 ? sm.cnt[nblk] : 0;
-        for (int b0 = 0, bi = 0; b0 < npairs; b0 += C::PB, ++bi) {
+        // ---- 4. piece products, PB at a time, then each owner sums its rows --------------
+        const int npieces = nblk > 0 ? pco[nblk] : 0;
+        for (int b0 = 0, bi = 0; b0 < npieces; b0 += C::PB, ++bi) {
             unsigned long long *touch = sm.touch + (bi & 1) * kGroups;
-            {   // thread -> pair b0 + tid % PB, rows (tid / PB) * RPT onwards
+            {   // thread -> piece b0 + tid % PB, rows (tid / PB) * 3 onwards
                 const int pi = b0 + tid % C::PB;
-                if (pi < npairs) {
-                    const unsigned e = sm.pairs[pi];
-                    const int la = e & 1023, lb = (e >> 10) & 1023, fl = e >> 20;
+                if (pi < npieces) {
+                    const int r0 = C::kPiece > 1 ? (int)pcs[pi] : pi;
+                    const int r1 = C::kPiece > 1 ? (int)pcs[pi + 1] : pi + 1;
+                    const unsigned e = sm.pairs[r0];
+                    const int fl = e >> 20;
                     Real *out = sm.prod + (pi - b0) * C::PS;
-                    if (tid < C::PB) {   // the first pair of a block in this batch marks the block
-                        const int ka = sm.oka[la], kb = sm.oka[lb];
+                    if (tid < C::PB) {   // the first piece of a block in this batch marks the block
+                        const int ka = sm.oka[e & 1023], kb = sm.oka[(e >> 10) & 1023];
                         const int B = block_id(ka, kb, Kopt);
-                        if (pi == b0 || pi == sm.cnt[B])
+                        if (pi == b0 || pi == pco[B])
                             __hip_atomic_fetch_or(&touch[B % kGroups], 1ull << (B / kGroups), __ATOMIC_RELAXED,
                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+                        piece_product<0>(sm, r0, r1, fl, out);
+                    } else {
+                        piece_product<3>(sm, r0, r1, fl, out);
                     }
-                    if (C::RPT == 6) pair_product<0, 6>(sm, la, lb, fl, out);
-                    else if (tid < C::PB) pair_product<0, 3>(sm, la, lb, fl, out);
-                    else pair_product<3, 3>(sm, la, lb, fl, out);
                 }
             }
             __syncthreads();
@@ -487,8 +592,8 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             for (int k = 0; k < kSlots; ++k) {
                 if (!((live >> k) & 1)) continue;
                 const int B = grp + kGroups * k;
-                const int p0 = max(sm.cnt[B], b0) - b0, p1 = min(sm.cnt[B + 1], b0 + C::PB) - b0;
-                int pi = p0;   // four products per step: their loads are independent
+                const int p0 = max(pco[B], b0) - b0, p1 = min(pco[B + 1], b0 + C::PB) - b0;
+                int pi = p0;   // four pieces per step: their loads are independent
                 for (; pi + 4 <= p1; pi += 4)
                     acc[k] += ((double)col[pi * C::PS] + (double)col[(pi + 1) * C::PS]) +
                               ((double)col[(pi + 2) * C::PS] + (double)col[(pi + 3) * C::PS]);

@@ -1,0 +1,156 @@
+// Point order for the linearisation.  Within each window the points are sorted by the
+// lowest, then the highest, optimisable keyframe that observes them; points that no
+// optimisable keyframe observes go last, and ties keep their index order.  The order
+// only changes which points the linearisation kernel groups into one chunk: consecutive
+// points of this order share most of their keyframes, so a chunk touches few camera
+// blocks of the reduced system and each touched block gathers many pairs.  The sums it
+// forms are the same (the Schur complement does not depend on the order of the points).
+//
+// The FP64 form, whose one-pair pieces make long runs of one block a load imbalance,
+// keeps the index order (k_order_identity writes it).  The mixed form uses two kernels,
+// run once per solve after the input checks:
+//   k_order_keys  grid (x, window), one thread per point: key = lowest | highest << 5;
+//   k_order       one 1024-thread block per window: two stable counting-sort passes over
+//                 32 buckets (by the highest, then by the lowest), each ranking a round
+//                 of 1024 points with one ballot per bucket per wavefront.  The window's
+//                 keys are staged in LDS when they fit.  The second pass writes, per
+//                 position of the order, the point, its first observation and its
+//                 observation count.
+// The result is deterministic.
+#include "lba_internal.h"
+
+#include <algorithm>
+
+namespace lba {
+
+constexpr int kOrdThreads = 1024;
+constexpr int kOrdWaves = kOrdThreads / kWave;
+constexpr int kBuckets = 32;             // optimisable keyframe index (below 30); 31 = none
+constexpr int kOrdLdsPoints = 49152;     // windows up to this many points sort from LDS keys
+static_assert(kMaxKoptFP64 < kBuckets - 1 && kMaxKoptMixed < kBuckets - 1, "keyframe digit range");
+
+__global__ __launch_bounds__(256) void k_order_identity(OrderArgs a) {
+    const WinInfo W = a.win[blockIdx.y];
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < W.M; i += gridDim.x * blockDim.x) {
+        const int P = W.pt0 + i;
+        const int s = a.pt_start[P];
+        a.pinfo[P] = make_int4(P, s, a.pt_start[P + 1] - s, 0);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_order_keys(OrderArgs a) {
+    const WinInfo W = a.win[blockIdx.y];
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < W.M; i += gridDim.x * blockDim.x) {
+        const int P = W.pt0 + i;
+        const int o0 = a.pt_start[P], o1 = a.pt_start[P + 1];
+        int lo = kBuckets - 1, hi = 0;
+        for (int o = o0; o < o1; o += 4) {   // four observations per step: independent loads
+            int kf[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) kf[u] = o + u < o1 ? a.obs_kf[o + u] : -1;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = kf[u] >= 0 ? a.opt_map[W.kf0 + kf[u]] : -1;
+                if (k >= 0) {
+                    lo = min(lo, k);
+                    hi = max(hi, k);
+                }
+            }
+        }
+        if (lo == kBuckets - 1) hi = kBuckets - 1;
+        a.keys[P] = (uint16_t)(lo | (hi << 5));
+    }
+}
+
+// one stable counting-sort pass over the window's M points: element i of the input order
+// is src[i] (window-local; the identity without src), its bucket the 5-bit digit of its
+// key at bit sh.  The element goes to place pos of the output: dst[pos] (window-local),
+// or, in the last pass, pinfo[pos].
+template <bool kLast>
+__device__ void order_pass(const OrderArgs &a, const WinInfo &W, const uint16_t *key, const int32_t *src,
+                           int32_t *dst, int sh, int *base, int *wcnt) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, M = W.M;
+    if (tid < kBuckets) base[tid] = 0;
+    __syncthreads();
+    for (int i = tid; i < M; i += kOrdThreads) {
+        const int e = src ? src[i] : i;
+        atomicAdd(&base[(key[e] >> sh) & (kBuckets - 1)], 1);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int s = 0;
+        for (int b = 0; b < kBuckets; ++b) {
+            const int c = base[b];
+            base[b] = s;
+            s += c;
+        }
+    }
+    __syncthreads();
+    for (int r = 0; r < M; r += kOrdThreads) {
+        const int i = r + tid;
+        const bool valid = i < M;
+        const int e = valid ? (src ? src[i] : i) : -1;
+        const int d = valid ? (key[e] >> sh) & (kBuckets - 1) : -1;
+        int ps = 0, pe = 0;
+        if (kLast && valid) {   // in flight during the ranking
+            ps = a.pt_start[W.pt0 + e];
+            pe = a.pt_start[W.pt0 + e + 1];
+        }
+        int rank = 0, mine = 0;
+        for (int b = 0; b < kBuckets; ++b) {
+            const unsigned long long bal = __ballot(d == b);
+            if (d == b) rank = __popcll(bal & ((1ull << lane) - 1ull));
+            if (lane == b) mine = __popcll(bal);
+        }
+        if (lane < kBuckets) wcnt[wave * kBuckets + lane] = mine;
+        __syncthreads();
+        if (valid) {
+            int pos = base[d] + rank;
+            for (int w = 0; w < wave; ++w) pos += wcnt[w * kBuckets + d];
+            if (kLast) a.pinfo[W.pt0 + pos] = make_int4(W.pt0 + e, ps, pe - ps, 0);
+            else dst[pos] = e;
+        }
+        __syncthreads();
+        if (tid < kBuckets) {
+            int s = 0;
+            for (int w = 0; w < kOrdWaves; ++w) s += wcnt[w * kBuckets + tid];
+            base[tid] += s;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kOrdThreads) void k_order(OrderArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int base[kBuckets];
+    __shared__ int wcnt[kOrdWaves * kBuckets];
+    const WinInfo W = a.win[blockIdx.x];
+    const uint16_t *key = a.keys + W.pt0;
+    if (W.M <= kOrdLdsPoints) {
+        uint16_t *lk = reinterpret_cast<uint16_t *>(smem);
+        for (int i = threadIdx.x; i < W.M; i += kOrdThreads) lk[i] = key[i];
+        key = lk;
+    }
+    __syncthreads();
+    int32_t *tmp = a.tmp + W.pt0;
+    order_pass<false>(a, W, key, nullptr, tmp, 5, base, wcnt);   // by the highest keyframe
+    __syncthreads();
+    order_pass<true>(a, W, key, tmp, nullptr, 0, base, wcnt);    // then, stably, by the lowest
+}
+
+hipError_t launch_order(const OrderArgs &a, int n_windows, int max_points, hipStream_t s) {
+    if (n_windows <= 0) return hipSuccess;
+    const int bx = std::max(1, std::min(64, (max_points + 255) / 256));
+    if (!a.by_keyframes) {
+        hipLaunchKernelGGL(k_order_identity, dim3(bx, n_windows), dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_order_keys, dim3(bx, n_windows), dim3(256), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t lds = sizeof(uint16_t) * (size_t)std::min(max_points, kOrdLdsPoints);
+    hipLaunchKernelGGL(k_order, dim3(n_windows), dim3(kOrdThreads), lds, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace lba

@@ -73,6 +73,7 @@ constexpr size_t kGraphCache = 1024;
 struct Plan {
     int nw = 0;
     int64_t max_obs = 0;
+    int max_pts = 0;
     bool mixed = false;
     int waves = 4;
     std::vector<WinInfo> win;
@@ -89,7 +90,7 @@ struct Plan {
     // workspace byte offsets
     size_t o_win, o_tiles, o_order, o_opt, o_kfoff, o_ptoff, o_obsoff, o_upload_end;
     size_t o_ptstart, o_ctl, o_T, o_X0, o_X1, o_part, o_partr, o_partd, o_partu, o_red, o_redflag, o_dp, o_pf,
-        o_stats, o_err, total;
+        o_pkey, o_ptmp, o_pinfo, o_stats, o_err, total;
 };
 
 int choose_points_per_tile(const lba_options &opt, int64_t total_points) {
@@ -222,6 +223,7 @@ lba_status build_plan(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, Pl
         maxn = std::max(maxn, W.n);
         pl.max_En = std::max(pl.max_En, W.E + W.n);
         pl.max_obs = std::max<int64_t>(pl.max_obs, W.N);
+        pl.max_pts = std::max(pl.max_pts, W.M);
     }
     if (red > INT32_MAX) return set_error(ctx, LBA_ERR_UNSUPPORTED, "batch too large");
     // launch the tiles heaviest first (estimated observations times a cost growing with
@@ -283,6 +285,9 @@ lba_status build_plan(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, Pl
     pl.o_redflag = o; o = align256(o + sizeof(double) * nw);
     pl.o_dp = o;      o = align256(o + sizeof(double) * pl.dp_elems);
     pl.o_pf = o;      o = align256(o + sizeof(double) * 12 * std::max(P->n_pt, 1));
+    pl.o_pkey = o;    o = align256(o + sizeof(uint16_t) * std::max(P->n_pt, 1));
+    pl.o_ptmp = o;    o = align256(o + sizeof(int32_t) * std::max(P->n_pt, 1));
+    pl.o_pinfo = o;   o = align256(o + sizeof(int4) * std::max(P->n_pt, 1));
     pl.o_stats = o;   o = align256(o + sizeof(double) * LBA_STATS_LEN * nw);
     pl.o_err = o;     o = align256(o + sizeof(int32_t) * 16);
     pl.total = o;
@@ -547,6 +552,22 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
     HIPCHK(collect_timing(ctx));
     if (in_err) return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "invalid input: %s", describe_input_error(in_err).c_str());
 
+    // point order of the linearisation (the observation structure is fixed for the solve)
+    int4 *d_pinfo = static_cast<int4 *>(W_(pl.o_pinfo));
+    {
+        OrderArgs oa;
+        memset(&oa, 0, sizeof(oa));
+        oa.win = d_win;
+        oa.pt_start = d_ptstart;
+        oa.opt_map = d_opt;
+        oa.obs_kf = P->obs_kf;
+        oa.keys = static_cast<uint16_t *>(W_(pl.o_pkey));
+        oa.tmp = static_cast<int32_t *>(W_(pl.o_ptmp));
+        oa.pinfo = d_pinfo;
+        oa.by_keyframes = pl.mixed ? 1 : 0;
+        HIPCHK(timed(ctx, LBA_KCLASS_ORDER, s, [&] { return launch_order(oa, nw, pl.max_pts, s); }));
+    }
+
     const int ntiles = (int)pl.tiles.size();
     LinArgs la;
     memset(&la, 0, sizeof(la));
@@ -555,6 +576,7 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
     la.order = static_cast<const int32_t *>(W_(pl.o_order));
     la.opt_map = d_opt;
     la.pt_start = d_ptstart;
+    la.pinfo = d_pinfo;
     la.T = d_T;
     la.X0 = d_X0;
     la.X1 = d_X1;

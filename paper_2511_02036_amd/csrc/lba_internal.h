@@ -77,6 +77,9 @@ struct LinArgs {
     const int32_t *order;        // launch order: block b processes tile order[b]
     const int32_t *opt_map;      // global kf -> window-local optimisable index or -1
     const int32_t *pt_start;     // global point -> first global observation (n_pt + 1)
+    const int4 *pinfo;           // per position of the linearisation order (points sorted by
+                                 // keyframes within each window): point, first observation,
+                                 // observation count, 0
     const double *T;             // working poses
     const double *X0, *X1;       // point double buffer
     const Ctl *ctl;
@@ -89,6 +92,19 @@ struct LinArgs {
     int robust;
     int waves;
     SolveConsts c;
+};
+
+// point order of the linearisation (k_order)
+struct OrderArgs {
+    const WinInfo *win;
+    const int32_t *pt_start;     // global point -> first global observation (n_pt + 1)
+    const int32_t *opt_map;      // global kf -> window-local optimisable index or -1
+    const int32_t *obs_kf;       // window-local keyframe of each observation
+    uint16_t *keys;              // per point: lowest | highest << 5 optimisable keyframe (n_pt)
+    int32_t *tmp;                // per window, window-local order after the first pass (n_pt)
+    int4 *pinfo;                 // result, per position of the order: point, first observation,
+                                 // observation count, 0 (n_pt)
+    int by_keyframes;            // 1: sort by keyframes; 0: index order
 };
 
 struct ReduceArgs {
@@ -212,6 +228,7 @@ hipError_t launch_cholesky(const CholArgs &a, int n_windows, size_t lds, hipStre
 hipError_t launch_decide(const DecideArgs &a, int n_windows, hipStream_t s);
 hipError_t launch_init_reduce(const InitReduceArgs &a, int n_windows, hipStream_t s);
 hipError_t launch_setup(const MiscArgs &a, int n_windows, hipStream_t s);
+hipError_t launch_order(const OrderArgs &a, int n_windows, int max_points, hipStream_t s);
 hipError_t launch_validate(const MiscArgs &a, int n_windows, int64_t max_obs, hipStream_t s);
 hipError_t launch_flags(const MiscArgs &a, int n_windows, int64_t max_obs, hipStream_t s);
 hipError_t launch_finalize(const MiscArgs &a, int n_windows, hipStream_t s);

@@ -32,7 +32,7 @@ EXPORTS = ["lba_abi_version", "lba_status_string", "lba_default_options", "lba_c
 
 KERNEL_CLASSES = ["linearize", "linearize_init", "reduce", "cholesky", "update", "decide",
                   "init_reduce", "setup", "validate", "flags", "finalize", "cost_forward",
-                  "cost_backward"]
+                  "cost_backward", "order"]
 
 
 class Options(C.Structure):
