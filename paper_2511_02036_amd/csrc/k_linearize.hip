@@ -192,7 +192,8 @@ __device__ __forceinline__ int block_row(int B, int Kopt) {
     return ka;
 }
 
-// inclusive scan of one 64-bit value per thread over the block (512 threads)
+// inclusive scan of one 64-bit value per thread over the block (512 threads).  The
+// caller places a barrier between this and the next writer of scan[].
 __device__ __forceinline__ long long block_inclusive_scan64(long long v, int *scan, int tid) {
     const int lane = tid & 63, wave = tid >> 6;
     long long x = v;
@@ -210,11 +211,11 @@ __device__ __forceinline__ long long block_inclusive_scan64(long long v, int *sc
         const long long u = sc[w];
         add += w < wave ? u : 0;
     }
-    __syncthreads();
     return x + add;
 }
 
-// inclusive scan of one int per thread over the block (512 threads)
+// inclusive scan of one int per thread over the block (512 threads).  The caller places a
+// barrier between this and the next writer of scan[].
 __device__ __forceinline__ int block_inclusive_scan(int v, int *scan, int tid) {
     const int lane = tid & 63, wave = tid >> 6;
     int x = v;
@@ -231,7 +232,6 @@ __device__ __forceinline__ int block_inclusive_scan(int v, int *scan, int tid) {
         const int v = scan[w];
         add += w < wave ? v : 0;
     }
-    __syncthreads();
     return x + add;
 }
 
@@ -402,6 +402,13 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             }
         }
         Facc += rho;
+        // list counters of phase 3, cleared here so that phases 2 and 3 need no barrier
+        // between them (the previous chunk's last reads of them precede a barrier)
+        for (int B = tid; B < nblk; B += kNT) {
+            sm.cnt[B] = 0;
+            sm.cur[B] = 0;
+        }
+        if (tid < 2 * kGroups) sm.touch[tid] = 0ull;
         const int anydup = __syncthreads_or(dup);
 
         // ---- 2. per-point sums, point factor, staged Z_a, D_a, r_a ---------------------
@@ -415,7 +422,6 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
                 for (int i = 0; i < 3; ++i) bs[i] += sm.hs[m * 9 + 6 + i];
             }
         }
-        __syncthreads();
         double Li[6] = {0, 0, 0, 0, 0, 0};
         double t0 = 0, t1 = 0, t2 = 0;
         if (has) {
@@ -474,12 +480,6 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
                 lds_add(dst + 21 + i,
                         bpd[i] - ((double)Zr[i * 3] * t0 + (double)Zr[i * 3 + 1] * t1 + (double)Zr[i * 3 + 2] * t2));
         }
-        for (int B = tid; B < nblk; B += kNT) {
-            sm.cnt[B] = 0;
-            sm.cur[B] = 0;
-        }
-        if (tid < 2 * kGroups) sm.touch[tid] = 0ull;
-        __syncthreads();
 
         // ---- 3. pair lists sorted by camera block --------------------------------------
         // Without duplicate (point, camera) observations the pairs of block (kA, kB) are
