@@ -86,6 +86,34 @@ __device__ __forceinline__ void piece_product(const LinSmem<Real> &sm, int r0, i
     Real acc[kRegs ? 18 : 1];
 #pragma unroll
     for (int c = 0; c < (kRegs ? 18 : 1); ++c) acc[c] = (Real)0;
+    if constexpr (kRegs) {
+        if (fl == 0) {   // the common case, unrolled without branches: all the piece's list
+                         // entries load at once, a missing pair repeats the last with weight 0
+            constexpr int NP = LinCfg<Real>::kPiece;
+            unsigned e[NP];
+#pragma unroll
+            for (int u = 0; u < NP; ++u) e[u] = sm.pairs[min(r0 + u, r1 - 1)];
+#pragma unroll
+            for (int u = 0; u < NP; ++u) {
+                const Real wgt = r0 + u < r1 ? (Real)1 : (Real)0;
+                const Real *za = sm.Z + (e[u] & 1023) * 18 + R0 * 3, *zb = sm.Z + ((e[u] >> 10) & 1023) * 18;
+                Real ai[9];
+#pragma unroll
+                for (int c = 0; c < 9; ++c) ai[c] = za[c] * wgt;
+#pragma unroll
+                for (int j = 0; j < 6; ++j) {
+                    const Real b0 = zb[j * 3], b1 = zb[j * 3 + 1], b2 = zb[j * 3 + 2];
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) acc[i * 6 + j] += ai[i * 3] * b0 + ai[i * 3 + 1] * b1 + ai[i * 3 + 2] * b2;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 6; ++j) out[(R0 + i) * 6 + j] = -acc[i * 6 + j];
+            return;
+        }
+    }
     for (int r = r0; r < r1; ++r) {
         const unsigned e = sm.pairs[r];
         const Real *za = sm.Z + (e & 1023) * 18, *zb = sm.Z + ((e >> 10) & 1023) * 18;
@@ -599,7 +627,9 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
                               ((double)col[(pi + 2) * C::PS] + (double)col[(pi + 3) * C::PS]);
                 for (; pi < p1; ++pi) acc[k] += (double)col[pi * C::PS];
             }
-            __syncthreads();
+            // the next batch overwrites the products; after the last one, the next chunk
+            // writes this region only after its first barrier
+            if (b0 + C::PB < npieces) __syncthreads();
         }
         p = q;
     }
