@@ -20,7 +20,7 @@
 //      two camera masks, and a pair's place is the number of the block's points before
 //      its own (a chunk with two observations of one point on one camera falls back to
 //      LDS integer atomics);
-//   4. each block's run of the list is cut into pieces of at most kPiece pairs (4 in
+//   4. each block's run of the list is cut into pieces of at most kPiece pairs (8 in
 //      FP32, 1 in FP64); in
 //      batches of PB pieces, two threads per piece (three rows each) write the piece's
 //      sum of -Z_a Z_b^T (lower triangle of Z_a Z_b^T + Z_b Z_a^T for two observations on
@@ -49,9 +49,9 @@ struct LinCfg {
     static constexpr int CO = sizeof(Real) == 4 ? 512 : 256;   // observations per chunk
     static constexpr int PCAP = sizeof(Real) == 4 ? 3072 : 2080;   // pairs per chunk (>= 64*65/2)
     static constexpr int PB = 256;                             // pieces per batch
-    // pairs per piece: FP32 sums up to four in registers; FP64, whose owner registers
+    // pairs per piece: FP32 sums up to eight in registers; FP64, whose owner registers
     // leave no room for 18 more doubles, takes one pair per piece
-    static constexpr int kPiece = sizeof(Real) == 4 ? 4 : 1;
+    static constexpr int kPiece = sizeof(Real) == 4 ? 8 : 1;
     static constexpr int PS = 37;                              // product row stride (odd)
     static constexpr int RPT = 6 * PB / kNT;                   // product rows per thread
     static_assert(RPT == 3, "two threads per piece");
