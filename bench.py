@@ -277,7 +277,7 @@ def main():
     ap.add_argument("--workload", default="c5_batched_mixed", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-window plain FP64 comparison")
-    ap.add_argument("--no-tune", action="store_true", help="batched workloads: skip the tile tuner")
+    ap.add_argument("--no-tune", action="store_true", help="skip the tile tuner")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 256 MiB device to device once (a kernel of known traffic that "
                          "calibrates hardware byte counters read by a profiler)")
@@ -314,8 +314,8 @@ def main():
     prob = lba.DeviceProblem(data, device=dev, z_f32=z_f32)
     stream = torch.cuda.current_stream(dev)
     tuned = None
-    if len(windows) > 1 and not args.no_tune:
-        # the tile tuner of the batched form (short solves; its table is kept in the context)
+    if not args.no_tune:
+        # the tile tuner (short solves; its table is kept in the context)
         t_tune = time.perf_counter()
         tuned = ctx.tune(prob, stream)
         print(f"bench: tile table {tuned} tuned in {time.perf_counter() - t_tune:.1f} s", file=sys.stderr, flush=True)

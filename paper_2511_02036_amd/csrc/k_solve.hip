@@ -26,25 +26,27 @@ __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a) {
         if (lane == 0) a.redflag[w] = fl;
     }
     if (blockIdx.x * 64 >= tot) return;
-    double s0 = 0.0, s1 = 0.0;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;   // four loads in flight per step
+    const double *src = nullptr;
+    int64_t stride = 0;
     if (i < W.E) {
-        const double *part = a.part + W.part_off;
-        int t = g;
-        for (; t + 4 < W.ntiles; t += 8) {
-            s0 += part[(int64_t)t * W.part_stride + i];
-            s1 += part[(int64_t)(t + 4) * W.part_stride + i];
-        }
-        for (; t < W.ntiles; t += 4) s0 += part[(int64_t)t * W.part_stride + i];
+        src = a.part + W.part_off + i;
+        stride = W.part_stride;
     } else if (i < tot) {
-        const double *pr = a.partr + W.partr_off + (i - W.E);
-        int t = g;
-        for (; t + 4 < W.ntiles; t += 8) {
-            s0 += pr[(int64_t)t * W.n];
-            s1 += pr[(int64_t)(t + 4) * W.n];
-        }
-        for (; t < W.ntiles; t += 4) s0 += pr[(int64_t)t * W.n];
+        src = a.partr + W.partr_off + (i - W.E);
+        stride = W.n;
     }
-    acc4[g][lane] = s0 + s1;
+    if (src) {
+        int t = g;
+        for (; t + 12 < W.ntiles; t += 16) {
+            s0 += src[(int64_t)t * stride];
+            s1 += src[(int64_t)(t + 4) * stride];
+            s2 += src[(int64_t)(t + 8) * stride];
+            s3 += src[(int64_t)(t + 12) * stride];
+        }
+        for (; t < W.ntiles; t += 4) s0 += src[(int64_t)t * stride];
+    }
+    acc4[g][lane] = (s0 + s1) + (s2 + s3);
     __syncthreads();
     if (g == 0 && i < tot) a.red[W.red_off + i] = (acc4[0][lane] + acc4[1][lane]) + (acc4[2][lane] + acc4[3][lane]);
 }
@@ -387,24 +389,44 @@ hipError_t launch_decide(const DecideArgs &a, int n_windows, hipStream_t s) {
 // ------------------------------------------------------------------------------------
 // damping initialisation of a round: F and lambda0 = tau * max diag(H)
 // ------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_init_reduce(InitReduceArgs a) {
-    __shared__ double smax[4];
+constexpr int kInitCols = 192;   // columns of one window's r (n = 6 Kopt <= 180), three per lane
+constexpr int kInitRedThreads = 1024;
+constexpr int kInitRedWaves = kInitRedThreads / 64;
+
+__global__ __launch_bounds__(kInitRedThreads) void k_init_reduce(InitReduceArgs a) {
+    __shared__ double smax[kInitRedWaves];
+    __shared__ double colsum[kInitRedWaves][kInitCols];
     const int w = blockIdx.x;
     const WinInfo W = a.win[w];
     Ctl *ctl = a.ctl + w;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    // largest diagonal entry of Hpp (per camera, summed over the tiles) ...
+    // largest diagonal entry of Hpp (per camera, summed over the tiles): wavefront g sums
+    // the tiles g, g + G, ... (G wavefronts, four tiles per step: twelve loads in flight),
+    // lane l the columns l, l + 64, l + 128 (coalesced rows) ...
+    constexpr int G = kInitRedWaves;
+    double cs[kInitCols / 64] = {};
+    const double *pr = a.partr + W.partr_off;
+    for (int t0 = wave; t0 < W.ntiles; t0 += 4 * G) {
+#pragma unroll
+        for (int c = 0; c < kInitCols / 64; ++c) {
+            const int col = lane + 64 * c;
+            double v = 0.0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int t = t0 + u * G;
+                if (col < W.n && t < W.ntiles) v += pr[(int64_t)t * W.n + col];
+            }
+            cs[c] += v;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < kInitCols / 64; ++c) colsum[wave][lane + 64 * c] = cs[c];
+    __syncthreads();
     double md = 0.0;
     for (int i = tid; i < W.n; i += blockDim.x) {
-        const double *pr = a.partr + W.partr_off + i;
-        double s0 = 0.0, s1 = 0.0;
-        int t = 0;
-        for (; t + 1 < W.ntiles; t += 2) {
-            s0 += pr[(int64_t)t * W.n];
-            s1 += pr[(int64_t)(t + 1) * W.n];
-        }
-        if (t < W.ntiles) s0 += pr[(int64_t)t * W.n];
-        md = fmax(md, s0 + s1);
+        double v = 0.0;
+        for (int g = 0; g < G; ++g) v += colsum[g][i];
+        md = fmax(md, v);
     }
     // ... and of the point blocks (per tile), and the cost
     double F = 0.0;
@@ -416,7 +438,8 @@ __global__ __launch_bounds__(256) void k_init_reduce(InitReduceArgs a) {
     if (lane == 0) smax[wave] = md;
     __syncthreads();
     if (tid == 0) {
-        md = fmax(fmax(smax[0], smax[1]), fmax(smax[2], smax[3]));
+        md = 0.0;
+        for (int g = 0; g < kInitRedWaves; ++g) md = fmax(md, smax[g]);
         if (a.round == 1) {
             ctl->F_initial = F;
         } else {
@@ -433,9 +456,11 @@ __global__ __launch_bounds__(256) void k_init_reduce(InitReduceArgs a) {
     }
 }
 
+static_assert(6 * kMaxKoptFP64 <= kInitCols && 6 * kMaxKoptMixed <= kInitCols, "columns per lane");
+
 hipError_t launch_init_reduce(const InitReduceArgs &a, int n_windows, hipStream_t s) {
     if (n_windows <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_init_reduce, dim3(n_windows), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_init_reduce, dim3(n_windows), dim3(kInitRedThreads), 0, s, a);
     return hipGetLastError();
 }
 
