@@ -1,8 +1,9 @@
 // Linearisation + Schur complement kernel (owner-computes).
 //
 // One 512-thread block per tile of one window's points, taken in the window's
-// linearisation order (points sorted by the keyframes that observe them, so that a
-// chunk's points share keyframes; the order is built once per solve).  The block's share
+// linearisation order (in windows with many optimisable keyframes, points sorted by the
+// keyframes that observe them, so that a chunk's points share keyframes; the order is
+// built once per solve).  The block's share
 // of the reduced camera system
 //     S = Hpp + lambda I - sum_j sum_{a,b in obs(j)} W_a V_j^-1 W_b^T,
 //     r = bp - sum_j sum_{a in obs(j)} W_a V_j^-1 bl_j,
@@ -21,12 +22,12 @@
 //      its own (a chunk with two observations of one point on one camera falls back to
 //      LDS integer atomics);
 //   4. each block's run of the list is cut into pieces of at most kPiece pairs (8 in
-//      FP32, 1 in FP64); in
-//      batches of PB pieces, two threads per piece (three rows each) write the piece's
-//      sum of -Z_a Z_b^T (lower triangle of Z_a Z_b^T + Z_b Z_a^T for two observations on
-//      one camera) to LDS in list order; 14 groups of 36 threads each own one entry of
-//      every 14th camera block and add up the contiguous run of their block's pieces in
-//      FP64 registers (no two threads add into the same entry, no atomics touch S).
+//      FP32, 4 in FP64); in batches of PB pieces, two threads per piece (three rows
+//      each) sum the piece's -Z_a Z_b^T (lower triangle of Z_a Z_b^T + Z_b Z_a^T for two
+//      observations on one camera) in registers and write it to LDS in list order; 14
+//      groups of 36 threads each own one entry of every 14th camera block and add up the
+//      contiguous run of their block's pieces in FP64 registers (no two threads add into
+//      the same entry, no atomics touch S).
 // At the end of the tile each owner writes its entry, plus the per-camera sums on the
 // diagonal blocks, to the tile's partial system; a separate kernel sums the partials of
 // a window in a fixed order (no global atomics).  The per-camera sums of step 2 are
@@ -49,9 +50,7 @@ struct LinCfg {
     static constexpr int CO = sizeof(Real) == 4 ? 512 : 256;   // observations per chunk
     static constexpr int PCAP = sizeof(Real) == 4 ? 3072 : 2080;   // pairs per chunk (>= 64*65/2)
     static constexpr int PB = 256;                             // pieces per batch
-    // pairs per piece: FP32 sums up to eight in registers; FP64, whose owner registers
-    // leave no room for 18 more doubles, takes one pair per piece
-    static constexpr int kPiece = sizeof(Real) == 4 ? 8 : 1;
+    static constexpr int kPiece = sizeof(Real) == 4 ? 8 : 4;   // pairs per piece (measured best)
     static constexpr int PS = 37;                              // product row stride (odd)
     static constexpr int RPT = 6 * PB / kNT;                   // product rows per thread
     static_assert(RPT == 3, "two threads per piece");
@@ -78,92 +77,60 @@ struct LinSmem {
 };
 
 // rows R0 .. R0 + 2 of the signed 6 x 6 sum over the pairs [r0, r1) of one piece (all
-// of one camera block, so all with the same flag).  Pieces of several pairs sum in
-// registers; one-pair pieces (FP64) write the product straight to their LDS row.
+// of one camera block, so all with the same flag), summed in registers
 template <int R0, typename Real>
 __device__ __forceinline__ void piece_product(const LinSmem<Real> &sm, int r0, int r1, int fl, Real *out) {
-    constexpr bool kRegs = LinCfg<Real>::kPiece > 1;
-    Real acc[kRegs ? 18 : 1];
+    Real acc[18];
 #pragma unroll
-    for (int c = 0; c < (kRegs ? 18 : 1); ++c) acc[c] = (Real)0;
-    if constexpr (kRegs) {
-        if (fl == 0) {   // the common case, unrolled without branches: all the piece's list
-                         // entries load at once, a missing pair repeats the last with weight 0
-            constexpr int NP = LinCfg<Real>::kPiece;
-            unsigned e[NP];
+    for (int c = 0; c < 18; ++c) acc[c] = (Real)0;
+    if (fl == 0) {   // Z_a Z_b^T, camera of a before camera of b; unrolled without branches:
+                     // all the piece's list entries load at once, a missing pair repeats
+                     // the last with weight 0
+        constexpr int NP = LinCfg<Real>::kPiece;
+        unsigned e[NP];
 #pragma unroll
-            for (int u = 0; u < NP; ++u) e[u] = sm.pairs[min(r0 + u, r1 - 1)];
+        for (int u = 0; u < NP; ++u) e[u] = sm.pairs[min(r0 + u, r1 - 1)];
 #pragma unroll
-            for (int u = 0; u < NP; ++u) {
-                const Real wgt = r0 + u < r1 ? (Real)1 : (Real)0;
-                const Real *za = sm.Z + (e[u] & 1023) * 18 + R0 * 3, *zb = sm.Z + ((e[u] >> 10) & 1023) * 18;
-                Real ai[9];
+        for (int u = 0; u < NP; ++u) {
+            const Real wgt = r0 + u < r1 ? (Real)1 : (Real)0;
+            const Real *za = sm.Z + (e[u] & 1023) * 18 + R0 * 3, *zb = sm.Z + ((e[u] >> 10) & 1023) * 18;
+            Real ai[9];
 #pragma unroll
-                for (int c = 0; c < 9; ++c) ai[c] = za[c] * wgt;
-#pragma unroll
-                for (int j = 0; j < 6; ++j) {
-                    const Real b0 = zb[j * 3], b1 = zb[j * 3 + 1], b2 = zb[j * 3 + 2];
-#pragma unroll
-                    for (int i = 0; i < 3; ++i) acc[i * 6 + j] += ai[i * 3] * b0 + ai[i * 3 + 1] * b1 + ai[i * 3 + 2] * b2;
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-                for (int j = 0; j < 6; ++j) out[(R0 + i) * 6 + j] = -acc[i * 6 + j];
-            return;
-        }
-    }
-    for (int r = r0; r < r1; ++r) {
-        const unsigned e = sm.pairs[r];
-        const Real *za = sm.Z + (e & 1023) * 18, *zb = sm.Z + ((e >> 10) & 1023) * 18;
-        const bool first = !kRegs || r == r0;   // one-pair pieces write, never add
-        Real ai[9];
-#pragma unroll
-        for (int c = 0; c < 9; ++c) ai[c] = za[R0 * 3 + c];
-        if (fl == 0) {   // Z_a Z_b^T, camera of a before camera of b
+            for (int c = 0; c < 9; ++c) ai[c] = za[c] * wgt;
 #pragma unroll
             for (int j = 0; j < 6; ++j) {
                 const Real b0 = zb[j * 3], b1 = zb[j * 3 + 1], b2 = zb[j * 3 + 2];
 #pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    const Real v = ai[i * 3] * b0 + ai[i * 3 + 1] * b1 + ai[i * 3 + 2] * b2;
-                    if constexpr (kRegs) acc[i * 6 + j] += v;
-                    else {
-                        Real *o = out + (R0 + i) * 6 + j;
-                        *o = first ? -v : *o - v;
-                    }
-                }
+                for (int i = 0; i < 3; ++i) acc[i * 6 + j] += ai[i * 3] * b0 + ai[i * 3 + 1] * b1 + ai[i * 3 + 2] * b2;
             }
-        } else {         // one camera twice: Z_a Z_b^T + Z_b Z_a^T, lower triangle
-            Real bi[9];
+        }
+    } else {         // one camera twice: Z_a Z_b^T + Z_b Z_a^T, lower triangle
+        for (int r = r0; r < r1; ++r) {
+            const unsigned e = sm.pairs[r];
+            const Real *za = sm.Z + (e & 1023) * 18, *zb = sm.Z + ((e >> 10) & 1023) * 18;
+            Real ai[9], bi[9];
 #pragma unroll
-            for (int c = 0; c < 9; ++c) bi[c] = zb[R0 * 3 + c];
+            for (int c = 0; c < 9; ++c) {
+                ai[c] = za[R0 * 3 + c];
+                bi[c] = zb[R0 * 3 + c];
+            }
 #pragma unroll
             for (int j = 0; j < R0 + 3; ++j) {
                 const Real b0 = zb[j * 3], b1 = zb[j * 3 + 1], b2 = zb[j * 3 + 2];
                 const Real a0 = za[j * 3], a1 = za[j * 3 + 1], a2 = za[j * 3 + 2];
 #pragma unroll
                 for (int i = 0; i < 3; ++i)
-                    if (j <= R0 + i) {
-                        const Real v = ai[i * 3] * b0 + ai[i * 3 + 1] * b1 + ai[i * 3 + 2] * b2 + bi[i * 3] * a0 +
-                                       bi[i * 3 + 1] * a1 + bi[i * 3 + 2] * a2;
-                        if constexpr (kRegs) acc[i * 6 + j] += v;
-                        else {
-                            Real *o = out + (R0 + i) * 6 + j;
-                            *o = first ? -v : *o - v;
-                        }
-                    }
+                    if (j <= R0 + i)
+                        acc[i * 6 + j] += ai[i * 3] * b0 + ai[i * 3 + 1] * b1 + ai[i * 3 + 2] * b2 + bi[i * 3] * a0 +
+                                          bi[i * 3 + 1] * a1 + bi[i * 3 + 2] * a2;
             }
         }
     }
-    if constexpr (kRegs) {
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < 3; ++i)
 #pragma unroll
-            for (int j = 0; j < 6; ++j)
-                if (fl == 0 || j <= R0 + i) out[(R0 + i) * 6 + j] = -acc[i * 6 + j];
-    }
+        for (int j = 0; j < 6; ++j)
+            if (fl == 0 || j <= R0 + i) out[(R0 + i) * 6 + j] = -acc[i * 6 + j];
 }
 
 static __host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -266,8 +233,6 @@ __device__ __forceinline__ int block_inclusive_scan(int v, int *scan, int tid) {
 template <typename Real, typename ZT>
 __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
     using C = LinCfg<Real>;
-    // the mixed form takes the points in keyframe order; FP64 in index order
-    constexpr bool kSorted = sizeof(Real) == 4;
     extern __shared__ __align__(16) unsigned char smem[];
     const int t = a.order[blockIdx.x];
     const Tile tile = a.tiles[t];
@@ -353,8 +318,7 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             pst[tid + 1] = obs_incl;
             gst[tid] = ps;
             pid[tid] = P;
-            if (kSorted)
-                for (int i = obs_incl - m; i < obs_incl; ++i) seg[i] = tid;
+            for (int i = obs_incl - m; i < obs_incl; ++i) seg[i] = tid;
             xs[3 * tid] = Xs[3 * (int64_t)P];
             xs[3 * tid + 1] = Xs[3 * (int64_t)P + 1];
             xs[3 * tid + 2] = Xs[3 * (int64_t)P + 2];
@@ -363,35 +327,16 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
         int pl = 0, kl = 0, stereo = 0, oct = 0;
         bool act = false;
         double zu = 0, zv = 0, zr = 0;
-        bool has;
-        if (kSorted) {   // observation slot tid: observation tid - pst[pl] of chunk point pl
-            __syncthreads();
-            has = tid < pst[np];
-            if (has) {
-                pl = seg[tid];
-                const int o = gst[pl] + tid - pst[pl];
-                kl = a.obs.kf[o];
-                act = !a.mask || !a.mask[o];
-                stereo = a.obs.type[o];
-                oct = a.obs.oct[o];
-                load_z<ZT>(a.obs, o, zu, zv, zr);
-            }
-        } else {         // index order: the chunk's observations are contiguous, and their
-                         // loads are in flight together with the point loads above
-            const int o = a.pinfo[p].y + tid;
-            int jl = 0;
-            const bool inb = o < a.obs.n_obs;
-            if (inb) {
-                jl = a.obs.pt[o];
-                kl = a.obs.kf[o];
-                act = !a.mask || !a.mask[o];
-                stereo = a.obs.type[o];
-                oct = a.obs.oct[o];
-                load_z<ZT>(a.obs, o, zu, zv, zr);
-            }
-            __syncthreads();
-            has = tid < pst[np];
-            pl = W.pt0 + jl - p;
+        __syncthreads();
+        const bool has = tid < pst[np];
+        if (has) {   // observation slot tid: observation tid - pst[pl] of chunk point pl
+            pl = seg[tid];
+            const int o = gst[pl] + tid - pst[pl];
+            kl = a.obs.kf[o];
+            act = !a.mask || !a.mask[o];
+            stereo = a.obs.type[o];
+            oct = a.obs.oct[o];
+            load_z<ZT>(a.obs, o, zu, zv, zr);
         }
 
         // ---- 1. per-observation terms -------------------------------------------------

@@ -6,9 +6,10 @@
 // blocks of the reduced system and each touched block gathers many pairs.  The sums it
 // forms are the same (the Schur complement does not depend on the order of the points).
 //
-// The FP64 form, whose one-pair pieces make long runs of one block a load imbalance,
-// keeps the index order (k_order_identity writes it).  The mixed form uses two kernels,
-// run once per solve after the input checks:
+// Windows with few optimisable keyframes (kSortMinKopt or fewer), whose chunks touch few
+// camera blocks in any order, keep the index order (k_order_identity writes it; the
+// sort did not pay there in measurements).  The others use two kernels, run once per
+// solve after the input checks:
 //   k_order_keys  grid (x, window), one thread per point: key = lowest | highest << 5;
 //   k_order       one 1024-thread block per window: two stable counting-sort passes over
 //                 32 buckets (by the highest, then by the lowest), each ranking a round
@@ -27,10 +28,16 @@ constexpr int kOrdThreads = 1024;
 constexpr int kOrdWaves = kOrdThreads / kWave;
 constexpr int kBuckets = 32;             // optimisable keyframe index (below 30); 31 = none
 constexpr int kOrdLdsPoints = 49152;     // windows up to this many points sort from LDS keys
+constexpr int kSortMinKopt = 20;         // windows with more optimisable keyframes are sorted
+
+__device__ __forceinline__ bool sorted_window(const OrderArgs &a, const WinInfo &W) {
+    return a.by_keyframes && W.Kopt > kSortMinKopt;
+}
 static_assert(kMaxKoptFP64 < kBuckets - 1 && kMaxKoptMixed < kBuckets - 1, "keyframe digit range");
 
 __global__ __launch_bounds__(256) void k_order_identity(OrderArgs a) {
     const WinInfo W = a.win[blockIdx.y];
+    if (sorted_window(a, W)) return;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < W.M; i += gridDim.x * blockDim.x) {
         const int P = W.pt0 + i;
         const int s = a.pt_start[P];
@@ -40,6 +47,7 @@ __global__ __launch_bounds__(256) void k_order_identity(OrderArgs a) {
 
 __global__ __launch_bounds__(256) void k_order_keys(OrderArgs a) {
     const WinInfo W = a.win[blockIdx.y];
+    if (!sorted_window(a, W)) return;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < W.M; i += gridDim.x * blockDim.x) {
         const int P = W.pt0 + i;
         const int o0 = a.pt_start[P], o1 = a.pt_start[P + 1];
@@ -125,6 +133,7 @@ __global__ __launch_bounds__(kOrdThreads) void k_order(OrderArgs a) {
     __shared__ int base[kBuckets];
     __shared__ int wcnt[kOrdWaves * kBuckets];
     const WinInfo W = a.win[blockIdx.x];
+    if (!sorted_window(a, W)) return;
     const uint16_t *key = a.keys + W.pt0;
     if (W.M <= kOrdLdsPoints) {
         uint16_t *lk = reinterpret_cast<uint16_t *>(smem);
@@ -138,15 +147,14 @@ __global__ __launch_bounds__(kOrdThreads) void k_order(OrderArgs a) {
     order_pass<true>(a, W, key, tmp, nullptr, 0, base, wcnt);    // then, stably, by the lowest
 }
 
-hipError_t launch_order(const OrderArgs &a, int n_windows, int max_points, hipStream_t s) {
+hipError_t launch_order(const OrderArgs &a, int n_windows, int max_points, int max_kopt, hipStream_t s) {
     if (n_windows <= 0) return hipSuccess;
     const int bx = std::max(1, std::min(64, (max_points + 255) / 256));
-    if (!a.by_keyframes) {
-        hipLaunchKernelGGL(k_order_identity, dim3(bx, n_windows), dim3(256), 0, s, a);
-        return hipGetLastError();
-    }
-    hipLaunchKernelGGL(k_order_keys, dim3(bx, n_windows), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_order_identity, dim3(bx, n_windows), dim3(256), 0, s, a);
     hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !a.by_keyframes || max_kopt <= kSortMinKopt) return e;
+    hipLaunchKernelGGL(k_order_keys, dim3(bx, n_windows), dim3(256), 0, s, a);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t lds = sizeof(uint16_t) * (size_t)std::min(max_points, kOrdLdsPoints);
     hipLaunchKernelGGL(k_order, dim3(n_windows), dim3(kOrdThreads), lds, s, a);

@@ -74,6 +74,7 @@ struct Plan {
     int nw = 0;
     int64_t max_obs = 0;
     int max_pts = 0;
+    int max_kopt = 0;
     bool mixed = false;
     int waves = 4;
     std::vector<WinInfo> win;
@@ -224,6 +225,7 @@ lba_status build_plan(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, Pl
         pl.max_En = std::max(pl.max_En, W.E + W.n);
         pl.max_obs = std::max<int64_t>(pl.max_obs, W.N);
         pl.max_pts = std::max(pl.max_pts, W.M);
+        pl.max_kopt = std::max(pl.max_kopt, W.Kopt);
     }
     if (red > INT32_MAX) return set_error(ctx, LBA_ERR_UNSUPPORTED, "batch too large");
     // launch the tiles heaviest first (estimated observations times a cost growing with
@@ -564,8 +566,8 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
         oa.keys = static_cast<uint16_t *>(W_(pl.o_pkey));
         oa.tmp = static_cast<int32_t *>(W_(pl.o_ptmp));
         oa.pinfo = d_pinfo;
-        oa.by_keyframes = pl.mixed ? 1 : 0;
-        HIPCHK(timed(ctx, LBA_KCLASS_ORDER, s, [&] { return launch_order(oa, nw, pl.max_pts, s); }));
+        oa.by_keyframes = 1;
+        HIPCHK(timed(ctx, LBA_KCLASS_ORDER, s, [&] { return launch_order(oa, nw, pl.max_pts, pl.max_kopt, s); }));
     }
 
     const int ntiles = (int)pl.tiles.size();

@@ -104,7 +104,8 @@ struct OrderArgs {
     int32_t *tmp;                // per window, window-local order after the first pass (n_pt)
     int4 *pinfo;                 // result, per position of the order: point, first observation,
                                  // observation count, 0 (n_pt)
-    int by_keyframes;            // 1: sort by keyframes; 0: index order
+    int by_keyframes;            // 1: sort the windows with many optimisable keyframes by
+                                 // keyframes; 0: index order everywhere
 };
 
 struct ReduceArgs {
@@ -228,7 +229,7 @@ hipError_t launch_cholesky(const CholArgs &a, int n_windows, size_t lds, hipStre
 hipError_t launch_decide(const DecideArgs &a, int n_windows, hipStream_t s);
 hipError_t launch_init_reduce(const InitReduceArgs &a, int n_windows, hipStream_t s);
 hipError_t launch_setup(const MiscArgs &a, int n_windows, hipStream_t s);
-hipError_t launch_order(const OrderArgs &a, int n_windows, int max_points, hipStream_t s);
+hipError_t launch_order(const OrderArgs &a, int n_windows, int max_points, int max_kopt, hipStream_t s);
 hipError_t launch_validate(const MiscArgs &a, int n_windows, int64_t max_obs, hipStream_t s);
 hipError_t launch_flags(const MiscArgs &a, int n_windows, int64_t max_obs, hipStream_t s);
 hipError_t launch_finalize(const MiscArgs &a, int n_windows, hipStream_t s);
