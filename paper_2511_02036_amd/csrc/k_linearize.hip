@@ -246,7 +246,7 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
     unsigned long long *const cm = sm.touch + 2 * kGroups;
     double *const xs = sm.hs + C::CO * 9;               // chunk point positions
     int *const pst = reinterpret_cast<int *>(xs + 3 * kNT);   // chunk-local observation starts
-    int *const gst = pst + kNT + 1;                     // first global observation of each point
+    int *const gst = pst + kNT + 1;                     // place of each point's first observation
     int *const pid = gst + kNT;                         // global index of each point
     int *const seg = pid + kNT;                         // chunk point of each observation slot
     int *const pco = sm.cnt + kMaxBlocks + 1;           // piece offsets per block
@@ -298,7 +298,7 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
         if (cand < tile.p1) {
             const int4 pi = a.pinfo[cand];
             P = pi.x;
-            ps = pi.y;
+            ps = pi.w;   // place of the point's first observation
             m = pi.z;
             inrange = 1;
         }
@@ -331,12 +331,12 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
         const bool has = tid < pst[np];
         if (has) {   // observation slot tid: observation tid - pst[pl] of chunk point pl
             pl = seg[tid];
-            const int o = gst[pl] + tid - pst[pl];
-            kl = a.obs.kf[o];
-            act = !a.mask || !a.mask[o];
-            stereo = a.obs.type[o];
-            oct = a.obs.oct[o];
-            load_z<ZT>(a.obs, o, zu, zv, zr);
+            const int o = gst[pl] + tid - pst[pl];   // the chunk's places are contiguous
+            kl = a.sobs.kf[o];
+            act = !a.smask || !a.smask[o];
+            stereo = a.sobs.type[o];
+            oct = a.sobs.oct[o];
+            load_z<ZT>(a.sobs, o, zu, zv, zr);
         }
 
         // ---- 1. per-observation terms -------------------------------------------------

@@ -16,8 +16,11 @@
 //                 of 1024 points with one ballot per bucket per wavefront.  The window's
 //                 keys are staged in LDS when they fit.  The second pass writes, per
 //                 position of the order, the point, its first observation and its
-//                 observation count.
-// The result is deterministic.
+//                 observation count; a last scan adds the place of the point's first
+//                 observation in the observation order that follows the points' order.
+// The result is deterministic.  k_order_gather then copies the observations into that
+// order (once per solve), and the outlier flags (once per round), so that the
+// linearisation reads each chunk's observations as one contiguous range.
 #include "lba_internal.h"
 
 #include <algorithm>
@@ -41,7 +44,7 @@ __global__ __launch_bounds__(256) void k_order_identity(OrderArgs a) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < W.M; i += gridDim.x * blockDim.x) {
         const int P = W.pt0 + i;
         const int s = a.pt_start[P];
-        a.pinfo[P] = make_int4(P, s, a.pt_start[P + 1] - s, 0);
+        a.pinfo[P] = make_int4(P, s, a.pt_start[P + 1] - s, s);
     }
 }
 
@@ -145,6 +148,91 @@ __global__ __launch_bounds__(kOrdThreads) void k_order(OrderArgs a) {
     order_pass<false>(a, W, key, nullptr, tmp, 5, base, wcnt);   // by the highest keyframe
     __syncthreads();
     order_pass<true>(a, W, key, tmp, nullptr, 0, base, wcnt);    // then, stably, by the lowest
+    __syncthreads();
+    // places of the observations: the window's first observation plus the exclusive
+    // prefix of the counts in the new order
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int carry = W.ob0;
+    for (int r = 0; r < W.M; r += kOrdThreads) {
+        const int i = r + tid;
+        const int m = i < W.M ? a.pinfo[W.pt0 + i].z : 0;
+        int x = m;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wcnt[wave] = x;
+        __syncthreads();
+        int add = carry, tot = 0;
+        for (int w = 0; w < kOrdWaves; ++w) {
+            const int v = wcnt[w];
+            add += w < wave ? v : 0;
+            tot += v;
+        }
+        if (i < W.M) a.pinfo[W.pt0 + i].w = add + x - m;
+        carry += tot;
+        __syncthreads();
+    }
+}
+
+// Each wavefront takes 64 consecutive positions of the order; their places form one
+// contiguous range (a point's observations follow the previous position's, across
+// windows too).  The lanes walk that range 64 places at a time (coalesced writes); each
+// finds the point of its place by binary lifting over the lanes' inclusive counts.
+template <bool kMask>
+__global__ __launch_bounds__(256) void k_order_gather(OrderArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nwv = (int64_t)gridDim.x * (blockDim.x / 64);
+    for (int64_t b = ((int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6)) * 64; b < a.n_pt; b += nwv * 64) {
+        const int64_t pos = b + lane;
+        int4 pi = make_int4(0, 0, 0, 0);
+        if (pos < a.n_pt) pi = a.pinfo[pos];
+        int incl = pi.z;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += y;
+        }
+        const int total = __shfl(incl, 63, 64);
+        const int first = __shfl(pi.w, 0, 64);   // place of the range's first observation
+        for (int d0 = 0; d0 < total; d0 += 64) {   // uniform trip count: every lane shuffles
+            const int d = d0 + lane;
+            int j = 0;   // the first lane whose inclusive count exceeds d (fixed six steps)
+#pragma unroll
+            for (int step = 32; step > 0; step >>= 1)
+                if (__shfl(incl, j + step - 1, 64) <= d) j += step;
+            const int excl = __shfl(incl, j, 64) - __shfl(pi.z, j, 64);
+            const int o = __shfl(pi.y, j, 64) + (d - excl), dst = first + d;
+            if (d >= total) continue;
+            if (kMask) {
+                a.smask[dst] = a.mask[o];
+            } else {
+                a.sobs_kf[dst] = a.obs.kf[o];
+                a.sobs_type[dst] = a.obs.type[o];
+                a.sobs_oct[dst] = a.obs.oct[o];
+                if (a.obs.z_f32) {
+                    const float *z = static_cast<const float *>(a.obs.z);
+                    float *sz = static_cast<float *>(a.sobs_z);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) sz[(int64_t)c * a.obs.n_obs + dst] = z[(int64_t)c * a.obs.n_obs + o];
+                } else {
+                    const double *z = static_cast<const double *>(a.obs.z);
+                    double *sz = static_cast<double *>(a.sobs_z);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) sz[(int64_t)c * a.obs.n_obs + dst] = z[(int64_t)c * a.obs.n_obs + o];
+                }
+            }
+        }
+    }
+}
+
+hipError_t launch_order_gather(const OrderArgs &a, bool mask, hipStream_t s) {
+    if (a.n_pt <= 0) return hipSuccess;
+    const int blocks = (int)std::min<int64_t>(4096, (a.n_pt + 255) / 256);   // 64 positions per wavefront
+    if (mask) hipLaunchKernelGGL(k_order_gather<true>, dim3(blocks), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_order_gather<false>, dim3(blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_order(const OrderArgs &a, int n_windows, int max_points, int max_kopt, hipStream_t s) {

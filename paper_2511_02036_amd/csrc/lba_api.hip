@@ -91,7 +91,7 @@ struct Plan {
     // workspace byte offsets
     size_t o_win, o_tiles, o_order, o_opt, o_kfoff, o_ptoff, o_obsoff, o_upload_end;
     size_t o_ptstart, o_ctl, o_T, o_X0, o_X1, o_part, o_partr, o_partd, o_partu, o_red, o_redflag, o_dp, o_pf,
-        o_pkey, o_ptmp, o_pinfo, o_stats, o_err, total;
+        o_pkey, o_ptmp, o_pinfo, o_skf, o_stype, o_soct, o_sz, o_smask, o_stats, o_err, total;
 };
 
 int choose_points_per_tile(const lba_options &opt, int64_t total_points) {
@@ -290,6 +290,13 @@ lba_status build_plan(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, Pl
     pl.o_pkey = o;    o = align256(o + sizeof(uint16_t) * std::max(P->n_pt, 1));
     pl.o_ptmp = o;    o = align256(o + sizeof(int32_t) * std::max(P->n_pt, 1));
     pl.o_pinfo = o;   o = align256(o + sizeof(int4) * std::max(P->n_pt, 1));
+    // the observations copied into the linearisation order
+    const size_t nob = (size_t)std::max(P->n_obs, 1);
+    pl.o_skf = o;     o = align256(o + sizeof(int32_t) * nob);
+    pl.o_stype = o;   o = align256(o + nob);
+    pl.o_soct = o;    o = align256(o + nob);
+    pl.o_sz = o;      o = align256(o + 3 * nob * (P->obs_z_f32 ? sizeof(float) : sizeof(double)));
+    pl.o_smask = o;   o = align256(o + nob);
     pl.o_stats = o;   o = align256(o + sizeof(double) * LBA_STATS_LEN * nw);
     pl.o_err = o;     o = align256(o + sizeof(int32_t) * 16);
     pl.total = o;
@@ -554,11 +561,18 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
     HIPCHK(collect_timing(ctx));
     if (in_err) return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "invalid input: %s", describe_input_error(in_err).c_str());
 
-    // point order of the linearisation (the observation structure is fixed for the solve)
+    // point order of the linearisation (the observation structure is fixed for the solve),
+    // and the observations copied into it
     int4 *d_pinfo = static_cast<int4 *>(W_(pl.o_pinfo));
+    ObsView sob = ob;
+    sob.pt = nullptr;
+    sob.kf = static_cast<const int32_t *>(W_(pl.o_skf));
+    sob.type = static_cast<const uint8_t *>(W_(pl.o_stype));
+    sob.oct = static_cast<const uint8_t *>(W_(pl.o_soct));
+    sob.z = W_(pl.o_sz);
+    OrderArgs oa;
+    memset(&oa, 0, sizeof(oa));
     {
-        OrderArgs oa;
-        memset(&oa, 0, sizeof(oa));
         oa.win = d_win;
         oa.pt_start = d_ptstart;
         oa.opt_map = d_opt;
@@ -567,7 +581,17 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
         oa.tmp = static_cast<int32_t *>(W_(pl.o_ptmp));
         oa.pinfo = d_pinfo;
         oa.by_keyframes = 1;
-        HIPCHK(timed(ctx, LBA_KCLASS_ORDER, s, [&] { return launch_order(oa, nw, pl.max_pts, pl.max_kopt, s); }));
+        oa.n_pt = P->n_pt;
+        oa.obs = ob;
+        oa.sobs_kf = static_cast<int32_t *>(W_(pl.o_skf));
+        oa.sobs_type = static_cast<uint8_t *>(W_(pl.o_stype));
+        oa.sobs_oct = static_cast<uint8_t *>(W_(pl.o_soct));
+        oa.sobs_z = W_(pl.o_sz);
+        oa.smask = static_cast<uint8_t *>(W_(pl.o_smask));
+        HIPCHK(timed(ctx, LBA_KCLASS_ORDER, s, [&] {
+            hipError_t e = launch_order(oa, nw, pl.max_pts, pl.max_kopt, s);
+            return e != hipSuccess ? e : launch_order_gather(oa, false, s);
+        }));
     }
 
     const int ntiles = (int)pl.tiles.size();
@@ -579,6 +603,7 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
     la.opt_map = d_opt;
     la.pt_start = d_ptstart;
     la.pinfo = d_pinfo;
+    la.sobs = sob;
     la.T = d_T;
     la.X0 = d_X0;
     la.X1 = d_X1;
@@ -652,11 +677,16 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
         const uint8_t *mask = nullptr;
         if (round == 2) {
             m.count = 0;
-            HIPCHK(timed(ctx, LBA_KCLASS_FLAGS, s, [&] { return launch_flags(m, nw, pl.max_obs, s); }));
+            oa.mask = R->outlier;
+            HIPCHK(timed(ctx, LBA_KCLASS_FLAGS, s, [&] {
+                hipError_t e = launch_flags(m, nw, pl.max_obs, s);
+                return e != hipSuccess ? e : launch_order_gather(oa, true, s);   // the flags in places
+            }));
             mask = R->outlier;
         }
         const int robust = round == 1 ? 1 : (opt.round2_robust ? 1 : 0);
         la.mask = mask;
+        la.smask = mask ? oa.smask : nullptr;
         la.robust = robust;
         ua.mask = mask;
         ua.robust = robust;

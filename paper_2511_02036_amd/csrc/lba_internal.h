@@ -79,7 +79,10 @@ struct LinArgs {
     const int32_t *pt_start;     // global point -> first global observation (n_pt + 1)
     const int4 *pinfo;           // per position of the linearisation order (points sorted by
                                  // keyframes within each window): point, first observation,
-                                 // observation count, 0
+                                 // observation count, place of the first observation in
+                                 // the observation order that follows the points' order
+    ObsView sobs;                // the observations in places (n_obs, same layout as obs)
+    const uint8_t *smask;        // round-2 outlier flags in places, or nullptr
     const double *T;             // working poses
     const double *X0, *X1;       // point double buffer
     const Ctl *ctl;
@@ -103,9 +106,17 @@ struct OrderArgs {
     uint16_t *keys;              // per point: lowest | highest << 5 optimisable keyframe (n_pt)
     int32_t *tmp;                // per window, window-local order after the first pass (n_pt)
     int4 *pinfo;                 // result, per position of the order: point, first observation,
-                                 // observation count, 0 (n_pt)
+                                 // observation count, place of the first observation (n_pt)
     int by_keyframes;            // 1: sort the windows with many optimisable keyframes by
                                  // keyframes; 0: index order everywhere
+    int32_t n_pt;
+    // observations copied into places (k_order_gather): the order that follows the points'
+    ObsView obs;                 // source, in index order
+    int32_t *sobs_kf;            // n_obs
+    uint8_t *sobs_type, *sobs_oct;
+    void *sobs_z;                // 3 x n_obs planar, the type of obs.z
+    const uint8_t *mask;         // k_order_gather_mask: outlier flags in index order ...
+    uint8_t *smask;              // ... and in places
 };
 
 struct ReduceArgs {
@@ -230,6 +241,7 @@ hipError_t launch_decide(const DecideArgs &a, int n_windows, hipStream_t s);
 hipError_t launch_init_reduce(const InitReduceArgs &a, int n_windows, hipStream_t s);
 hipError_t launch_setup(const MiscArgs &a, int n_windows, hipStream_t s);
 hipError_t launch_order(const OrderArgs &a, int n_windows, int max_points, int max_kopt, hipStream_t s);
+hipError_t launch_order_gather(const OrderArgs &a, bool mask, hipStream_t s);
 hipError_t launch_validate(const MiscArgs &a, int n_windows, int64_t max_obs, hipStream_t s);
 hipError_t launch_flags(const MiscArgs &a, int n_windows, int64_t max_obs, hipStream_t s);
 hipError_t launch_finalize(const MiscArgs &a, int n_windows, hipStream_t s);
