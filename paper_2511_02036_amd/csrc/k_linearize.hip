@@ -22,8 +22,8 @@
 //      its own (a chunk with two observations of one point on one camera falls back to
 //      LDS integer atomics);
 //   4. each block's run of the list is cut into pieces of at most kPiece pairs (8 in
-//      FP32, 4 in FP64); in batches of PB pieces, two threads per piece (three rows
-//      each) sum the piece's -Z_a Z_b^T (lower triangle of Z_a Z_b^T + Z_b Z_a^T for two
+//      FP32, 4 in FP64); in batches of PB pieces, two neighbouring threads per piece
+//      (three rows each, sharing Z_b through a lane swap) sum the piece's -Z_a Z_b^T (lower triangle of Z_a Z_b^T + Z_b Z_a^T for two
 //      observations on one camera) in registers and write it to LDS in list order; 14
 //      groups of 36 threads each own one entry of every 14th camera block and add up the
 //      contiguous run of their block's pieces in FP64 registers (no two threads add into
@@ -53,7 +53,7 @@ struct LinCfg {
     static constexpr int kPiece = sizeof(Real) == 4 ? 8 : 4;   // pairs per piece (measured best)
     static constexpr int PS = 37;                              // product row stride (odd)
     static constexpr int RPT = 6 * PB / kNT;                   // product rows per thread
-    static_assert(RPT == 3, "two threads per piece");
+    static_assert(RPT == 3, "two neighbouring threads per piece");
     static_assert(PCAP < 65536, "packed scan of pair and piece counts");
 };
 
@@ -76,35 +76,68 @@ struct LinSmem {
     double *red;     // 16 x 2
 };
 
-// rows R0 .. R0 + 2 of the signed 6 x 6 sum over the pairs [r0, r1) of one piece (all
-// of one camera block, so all with the same flag), summed in registers
-template <int R0, typename Real>
-__device__ __forceinline__ void piece_product(const LinSmem<Real> &sm, int r0, int r1, int fl, Real *out) {
-    Real acc[18];
-#pragma unroll
-    for (int c = 0; c < 18; ++c) acc[c] = (Real)0;
-    if (fl == 0) {   // Z_a Z_b^T, camera of a before camera of b; unrolled without branches:
-                     // all the piece's list entries load at once, a missing pair repeats
-                     // the last with weight 0
+// value of the neighbouring lane: lanes 2k and 2k + 1 exchange (DPP quad permutation
+// [1, 0, 3, 2], no LDS traffic); both lanes must be active
+template <typename Real>
+__device__ __forceinline__ Real lane_pair_swap(Real v) {
+    if constexpr (sizeof(Real) == 4) {
+        return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+    } else {
+        const long long b = __double_as_longlong(v);
+        const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0xB1, 0xF, 0xF, false);
+        const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0xB1, 0xF, 0xF, false);
+        return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+    }
+}
+
+// The signed 6 x 6 sum over the pairs [r0, r1) of one piece (all of one camera block, so
+// all with the same flag), by two neighbouring lanes: lane h of the pair forms rows 3h ..
+// 3h + 2, summed in registers.  For two cameras (the common case) each lane loads only
+// rows 3h .. 3h + 2 of Z_a and Z_b and takes the other half of Z_b from its neighbour;
+// the list entries of the piece load at once and the pairs are unrolled without branches
+// (a missing pair repeats the last with weight 0).
+template <typename Real>
+__device__ __forceinline__ void piece_product(const LinSmem<Real> &sm, int r0, int r1, int fl, int h, Real *out) {
+    const int R0 = 3 * h, R1 = 3 - R0;   // own rows, the neighbour's rows
+    if (fl == 0) {   // Z_a Z_b^T, camera of a before camera of b
         constexpr int NP = LinCfg<Real>::kPiece;
+        Real own[9], oth[9];   // [i][jj]: row R0 + i of the sum, column R0 + jj / R1 + jj
+#pragma unroll
+        for (int c = 0; c < 9; ++c) own[c] = oth[c] = (Real)0;
         unsigned e[NP];
 #pragma unroll
         for (int u = 0; u < NP; ++u) e[u] = sm.pairs[min(r0 + u, r1 - 1)];
 #pragma unroll
         for (int u = 0; u < NP; ++u) {
             const Real wgt = r0 + u < r1 ? (Real)1 : (Real)0;
-            const Real *za = sm.Z + (e[u] & 1023) * 18 + R0 * 3, *zb = sm.Z + ((e[u] >> 10) & 1023) * 18;
-            Real ai[9];
+            const Real *za = sm.Z + (e[u] & 1023) * 18 + R0 * 3, *zb = sm.Z + ((e[u] >> 10) & 1023) * 18 + R0 * 3;
+            Real ai[9], bh[9], bo[9];
 #pragma unroll
-            for (int c = 0; c < 9; ++c) ai[c] = za[c] * wgt;
-#pragma unroll
-            for (int j = 0; j < 6; ++j) {
-                const Real b0 = zb[j * 3], b1 = zb[j * 3 + 1], b2 = zb[j * 3 + 2];
-#pragma unroll
-                for (int i = 0; i < 3; ++i) acc[i * 6 + j] += ai[i * 3] * b0 + ai[i * 3 + 1] * b1 + ai[i * 3 + 2] * b2;
+            for (int c = 0; c < 9; ++c) {
+                ai[c] = za[c] * wgt;
+                bh[c] = zb[c];
             }
+#pragma unroll
+            for (int c = 0; c < 9; ++c) bo[c] = lane_pair_swap(bh[c]);
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int jj = 0; jj < 3; ++jj) {
+                    own[i * 3 + jj] += ai[i * 3] * bh[jj * 3] + ai[i * 3 + 1] * bh[jj * 3 + 1] + ai[i * 3 + 2] * bh[jj * 3 + 2];
+                    oth[i * 3 + jj] += ai[i * 3] * bo[jj * 3] + ai[i * 3 + 1] * bo[jj * 3 + 1] + ai[i * 3 + 2] * bo[jj * 3 + 2];
+                }
         }
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int jj = 0; jj < 3; ++jj) {
+                out[(R0 + i) * 6 + R0 + jj] = -own[i * 3 + jj];
+                out[(R0 + i) * 6 + R1 + jj] = -oth[i * 3 + jj];
+            }
     } else {         // one camera twice: Z_a Z_b^T + Z_b Z_a^T, lower triangle
+        Real acc[18];
+#pragma unroll
+        for (int c = 0; c < 18; ++c) acc[c] = (Real)0;
         for (int r = r0; r < r1; ++r) {
             const unsigned e = sm.pairs[r];
             const Real *za = sm.Z + (e & 1023) * 18, *zb = sm.Z + ((e >> 10) & 1023) * 18;
@@ -115,22 +148,21 @@ __device__ __forceinline__ void piece_product(const LinSmem<Real> &sm, int r0, i
                 bi[c] = zb[R0 * 3 + c];
             }
 #pragma unroll
-            for (int j = 0; j < R0 + 3; ++j) {
+            for (int j = 0; j < 6; ++j) {
                 const Real b0 = zb[j * 3], b1 = zb[j * 3 + 1], b2 = zb[j * 3 + 2];
                 const Real a0 = za[j * 3], a1 = za[j * 3 + 1], a2 = za[j * 3 + 2];
 #pragma unroll
                 for (int i = 0; i < 3; ++i)
-                    if (j <= R0 + i)
-                        acc[i * 6 + j] += ai[i * 3] * b0 + ai[i * 3 + 1] * b1 + ai[i * 3 + 2] * b2 + bi[i * 3] * a0 +
-                                          bi[i * 3 + 1] * a1 + bi[i * 3 + 2] * a2;
+                    acc[i * 6 + j] += ai[i * 3] * b0 + ai[i * 3 + 1] * b1 + ai[i * 3 + 2] * b2 + bi[i * 3] * a0 +
+                                      bi[i * 3 + 1] * a1 + bi[i * 3 + 2] * a2;
             }
         }
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 6; ++j)
+                if (j <= R0 + i) out[(R0 + i) * 6 + j] = -acc[i * 6 + j];
     }
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 6; ++j)
-            if (fl == 0 || j <= R0 + i) out[(R0 + i) * 6 + j] = -acc[i * 6 + j];
 }
 
 static __host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -536,24 +568,22 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
         const int npieces = nblk > 0 ? pco[nblk] : 0;
         for (int b0 = 0, bi = 0; b0 < npieces; b0 += C::PB, ++bi) {
             unsigned long long *touch = sm.touch + (bi & 1) * kGroups;
-            {   // thread -> piece b0 + tid % PB, rows (tid / PB) * 3 onwards
-                const int pi = b0 + tid % C::PB;
+            {   // neighbouring threads 2k, 2k + 1 -> piece b0 + k, rows 0 .. 2 / 3 .. 5
+                const int pi = b0 + (tid >> 1), h = tid & 1;
                 if (pi < npieces) {
                     const int r0 = C::kPiece > 1 ? (int)pcs[pi] : pi;
                     const int r1 = C::kPiece > 1 ? (int)pcs[pi + 1] : pi + 1;
                     const unsigned e = sm.pairs[r0];
                     const int fl = e >> 20;
                     Real *out = sm.prod + (pi - b0) * C::PS;
-                    if (tid < C::PB) {   // the first piece of a block in this batch marks the block
+                    if (h == 0) {   // the first piece of a block in this batch marks the block
                         const int ka = sm.oka[e & 1023], kb = sm.oka[(e >> 10) & 1023];
                         const int B = block_id(ka, kb, Kopt);
                         if (pi == b0 || pi == pco[B])
                             __hip_atomic_fetch_or(&touch[B % kGroups], 1ull << (B / kGroups), __ATOMIC_RELAXED,
                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
-                        piece_product<0>(sm, r0, r1, fl, out);
-                    } else {
-                        piece_product<3>(sm, r0, r1, fl, out);
                     }
+                    piece_product<Real>(sm, r0, r1, fl, h, out);
                 }
             }
             __syncthreads();
