@@ -181,11 +181,12 @@ lba_status lba_solve_batch(lba_ctx *ctx, const lba_problem *problem, const lba_b
                            lba_result *result, void *workspace, size_t workspace_bytes,
                            void *stream);
 
-/* Tile tuner of the batched form.  The linearisation and update kernels run one block per
- * tile of consecutive points of a window; the tile size trades per-tile work (the partial
- * reduced system each tile writes and the fixed-order sum over tiles) against the number
- * of blocks that fill the GPU.  lba_tune times short solves (three LM steps on every
- * window, on `stream`) of this problem with candidate tile sizes 64 ... 4096 points, one
+/* Tile tuner of the batched form.  The linearisation kernel runs one block per tile of
+ * a window's points (the update one block per part of a tile); the tile size trades
+ * per-tile work (the partial reduced system each tile writes and the fixed-order sum over
+ * tiles) against the number of blocks that fill the GPU.  lba_tune times short solves
+ * (three LM steps on every window, on `stream`; the least of three runs after a first
+ * that captures the step graph) of this problem with candidate tile sizes 64 ... 4096 points, one
  * value per class of windows by optimisable keyframes (<= 10, <= 20, > 20), by coordinate
  * descent, and keeps the fastest table in the context: later solves of a problem with the
  * same sizes and precision use it when points_per_tile is 0.  The problem's inputs are

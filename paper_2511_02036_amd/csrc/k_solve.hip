@@ -326,10 +326,11 @@ __global__ __launch_bounds__(64) void k_decide(DecideArgs a) {
     if (!ctl->running) return;
     const int lane = threadIdx.x;
     double Ft = 0.0, den = 0.0, fl = 0.0;
-    for (int t = lane; t < W.ntiles; t += 64) {
-        Ft += a.partu[4 * (W.tile0 + t)];
-        den += a.partu[4 * (W.tile0 + t) + 1];
-        fl = fmax(fl, a.partu[4 * (W.tile0 + t) + 2]);
+    const int64_t u0 = (int64_t)W.tile0 * a.split;   // the update's parts of this window's tiles
+    for (int t = lane; t < W.ntiles * a.split; t += 64) {
+        Ft += a.partu[4 * (u0 + t)];
+        den += a.partu[4 * (u0 + t) + 1];
+        fl = fmax(fl, a.partu[4 * (u0 + t) + 2]);
     }
     Ft = wave_sum(Ft);
     den = wave_sum(den) + ctl->denom_p;

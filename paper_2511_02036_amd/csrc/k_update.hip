@@ -76,7 +76,8 @@ __device__ inline UpdSmem<Real> carve_upd(unsigned char *base, int K, int n, int
 template <typename Real, typename ZT>
 __global__ __launch_bounds__(kUpdThreads) void k_update(UpdArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int tt = a.order[blockIdx.x];
+    // block b: part b % split of tile order[b / split] (the tile's points split evenly)
+    const int tt = a.order[blockIdx.x / a.split], sub = blockIdx.x % a.split;
     const Tile tile = a.tiles[tt];
     const WinInfo W = a.win[tile.win];
     const Ctl ctl = a.ctl[tile.win];
@@ -109,9 +110,11 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(UpdArgs a) {
     double *xs = sm.xs + wave * 64 * 3;
     int *pst = sm.pst + wave * 65;
     double *ps = sm.pslot + wave * 64 * 4;
-    const int np = tile.p1 - tile.p0;
-    const int wp0 = tile.p0 + (int)(((int64_t)np * wave) / waves);
-    const int wp1 = tile.p0 + (int)(((int64_t)np * (wave + 1)) / waves);
+    const int sp0 = tile.p0 + (int)(((int64_t)(tile.p1 - tile.p0) * sub) / a.split);
+    const int sp1 = tile.p0 + (int)(((int64_t)(tile.p1 - tile.p0) * (sub + 1)) / a.split);
+    const int np = sp1 - sp0;
+    const int wp0 = sp0 + (int)(((int64_t)np * wave) / waves);
+    const int wp1 = sp0 + (int)(((int64_t)np * (wave + 1)) / waves);
     const CamParams cam = a.c.cam;
     double Ftr = 0.0, den = 0.0;
     int fail = 0;
@@ -253,7 +256,7 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(UpdArgs a) {
             D += sm.red[w * 3 + 1];
             fl = fmax(fl, sm.red[w * 3 + 2]);
         }
-        const int t = tt;
+        const int64_t t = (int64_t)tt * a.split + sub;
         a.partu[4 * t] = F;
         a.partu[4 * t + 1] = D;
         a.partu[4 * t + 2] = fl;
@@ -263,7 +266,7 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(UpdArgs a) {
 
 hipError_t launch_update(const UpdArgs &a, int ntiles, size_t lds, bool mixed, hipStream_t s) {
     if (ntiles <= 0) return hipSuccess;
-    dim3 grid(ntiles), block(64 * a.waves);
+    dim3 grid(ntiles * a.split), block(64 * a.waves);
     const bool zf = a.obs.z_f32 != 0;
     if (mixed) {
         if (zf) hipLaunchKernelGGL((k_update<float, float>), grid, block, lds, s, a);

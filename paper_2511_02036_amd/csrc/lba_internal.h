@@ -151,7 +151,8 @@ struct UpdArgs {
     const double *pf;            // per point factors written by the linearisation of this step
     ObsView obs;
     const uint8_t *mask;
-    double *partu;               // 4 doubles per tile: F', denominator part, fail, unused
+    double *partu;               // 4 doubles per part of a tile: F', denominator part, fail, unused
+    int split;                   // parts per tile (one block each)
     int robust;
     int waves;
     SolveConsts c;
@@ -163,7 +164,8 @@ struct DecideArgs {
     const int32_t *opt_map;
     double *T;
     const double *dp;
-    const double *partu;
+    const double *partu;         // 4 doubles per part of a tile (split parts per tile)
+    int split;
     int round;                   // 1 or 2
     SolveConsts c;
 };
