@@ -157,3 +157,17 @@ def test_invalid_inputs_are_rejected_before_any_solve(breakage):
         w["obs_z"][0, 5] = np.nan
     with pytest.raises(lba.LBAError, match="invalid"):
         _gpu(w)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_large_tiles_split_across_update_blocks(precision):
+    """One tile of 3,000 points: the update kernel then runs the tile as several blocks
+    (parts of about 512 points) whose partial sums the decision adds."""
+    w = synth.tiny_window(29, K=12, n_fixed=3, M=3000, nobs=(3, 8), stereo_p=0.6)
+    g = _gpu(w, points_per_tile=4096, precision=precision)
+    r = lbaref.solve(w)
+    if precision == "fp64":
+        assert_fp64_parity(w, g["T"], g["X"], g["outlier"], g["stats"][0], r)
+    else:
+        from tests.parity import assert_mixed_tolerances
+        assert_mixed_tolerances(w, g["T"], g["X"], g["stats"][0], r)
