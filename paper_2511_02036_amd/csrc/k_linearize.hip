@@ -528,38 +528,47 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             }
         }
         __syncthreads();
-        if (ka >= 0) {
-            const int pw = pl >> 6;
-            const unsigned long long below = (1ull << (pl & 63)) - 1ull;
-            for (int b0 = tid + 1; b0 < s1; b0 += 4) {   // partners four at a time
-                int kb[4], B[4], rk[4];   // rk: place within the block's run
-#pragma unroll
-                for (int u = 0; u < 4; ++u) kb[u] = b0 + u < s1 ? sm.oka[b0 + u] : -1;
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int lo = min(ka, kb[u]), hi = max(ka, kb[u]);
-                    B[u] = block_id(lo, hi, Kopt);
-                    if (kb[u] < 0) continue;
-                    if (anydup) {
-                        rk[u] = atomicAdd(&sm.cur[B[u]], 1);
-                    } else {
-                        int r = __popcll(cm[lo * 8 + pw] & cm[hi * 8 + pw] & below);
-                        for (int w = 0; w < pw; ++w) r += __popcll(cm[lo * 8 + w] & cm[hi * 8 + w]);
-                        rk[u] = r;
-                    }
+        // Placement.  The pairs of one point are shared round-robin by all its observation
+        // threads (pair g of a point of m observations goes to its thread g mod m), so no
+        // thread places more than ceil((m - 1) / 2) of them; a chunk with a repeated
+        // observation places each observation's pairs with its later partners (atomics).
+        auto place = [&](int sa, int sb, int kA, int kB, int rk, int B) {
+            // first = the observation on the lower camera; flag 2 = two observations of
+            // one point on the same camera
+            const int first = kA <= kB ? sa : sb, second = kA <= kB ? sb : sa;
+            const unsigned fl = kA == kB ? 2u : 0u;
+            const int pos = sm.cnt[B] + rk;
+            sm.pairs[pos] = (unsigned)first | ((unsigned)second << 10) | (fl << 20);
+            if (C::kPiece > 1 && rk % C::kPiece == 0) pcs[pco[B] + rk / C::kPiece] = (unsigned)pos;
+        };
+        if (!anydup) {
+            if (has) {
+                const int pw = pl >> 6;
+                const unsigned long long below = (1ull << (pl & 63)) - 1ull;
+                const int mp = s1 - s0, npp = mp * (mp - 1) / 2;
+                for (int g = tid - s0; g < npp; g += mp) {
+                    // pair g = (a, b), a < b, in row order: row a starts at a m - a (a + 1) / 2
+                    const float c = 2.0f * mp - 1.0f;
+                    int ar = (int)((c - sqrtf(fmaxf(c * c - 8.0f * g, 0.0f))) * 0.5f);
+                    ar = min(max(ar, 0), mp - 2);
+                    if (ar > 0 && ar * mp - ar * (ar + 1) / 2 > g) --ar;
+                    if (ar + 1 <= mp - 2 && (ar + 1) * mp - (ar + 1) * (ar + 2) / 2 <= g) ++ar;
+                    const int br = ar + 1 + (g - (ar * mp - ar * (ar + 1) / 2));
+                    const int sa = s0 + ar, sb = s0 + br;
+                    const int kA = sm.oka[sa], kB = sm.oka[sb];
+                    if (kA < 0 || kB < 0) continue;
+                    const int lo = min(kA, kB), hi = max(kA, kB);
+                    int r = __popcll(cm[lo * 8 + pw] & cm[hi * 8 + pw] & below);
+                    for (int w = 0; w < pw; ++w) r += __popcll(cm[lo * 8 + w] & cm[hi * 8 + w]);
+                    place(sa, sb, kA, kB, r, block_id(lo, hi, Kopt));
                 }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    if (kb[u] < 0) continue;
-                    const int b = b0 + u;
-                    // first = the observation on the lower camera; flag 2 = two observations
-                    // of one point on the same camera
-                    const int first = ka <= kb[u] ? tid : b, second = ka <= kb[u] ? b : tid;
-                    const unsigned fl = ka == kb[u] ? 2u : 0u;
-                    const int pos = sm.cnt[B[u]] + rk[u];
-                    sm.pairs[pos] = (unsigned)first | ((unsigned)second << 10) | (fl << 20);
-                    if (C::kPiece > 1 && rk[u] % C::kPiece == 0) pcs[pco[B[u]] + rk[u] / C::kPiece] = (unsigned)pos;
-                }
+            }
+        } else if (ka >= 0) {
+            for (int b = tid + 1; b < s1; ++b) {
+                const int kb = sm.oka[b];
+                if (kb < 0) continue;
+                const int B = block_id(min(ka, kb), max(ka, kb), Kopt);
+                place(tid, b, ka, kb, atomicAdd(&sm.cur[B], 1), B);
             }
         }
         __syncthreads();
