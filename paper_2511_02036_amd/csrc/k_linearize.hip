@@ -2,9 +2,9 @@
 //
 // One 512-thread block per tile of one window's points, taken in the window's
 // linearisation order (in windows with many optimisable keyframes, points sorted by the
-// keyframes that observe them, so that a chunk's points share keyframes; the order is
-// built once per solve).  The block's share
-// of the reduced camera system
+// keyframes that observe them, so that a chunk's points share keyframes; the order and
+// the observations copied into it are built once per solve).  The block's share of the
+// reduced camera system
 //     S = Hpp + lambda I - sum_j sum_{a,b in obs(j)} W_a V_j^-1 W_b^T,
 //     r = bp - sum_j sum_{a in obs(j)} W_a V_j^-1 bl_j,
 // is assembled on chip for the whole tile.  The tile is walked in chunks of whole points
@@ -19,15 +19,16 @@
 //   3. every pair (a, b), a < b, of optimisable observations of one point is placed into
 //      a list sorted by camera block: the count of block (kA, kB) is the popcount of the
 //      two camera masks, and a pair's place is the number of the block's points before
-//      its own (a chunk with two observations of one point on one camera falls back to
-//      LDS integer atomics);
+//      its own; the threads of a point share its pairs round-robin (a chunk with two
+//      observations of one point on one camera falls back to LDS integer atomics);
 //   4. each block's run of the list is cut into pieces of at most kPiece pairs (8 in
 //      FP32, 4 in FP64); in batches of PB pieces, two neighbouring threads per piece
-//      (three rows each, sharing Z_b through a lane swap) sum the piece's -Z_a Z_b^T (lower triangle of Z_a Z_b^T + Z_b Z_a^T for two
-//      observations on one camera) in registers and write it to LDS in list order; 14
-//      groups of 36 threads each own one entry of every 14th camera block and add up the
-//      contiguous run of their block's pieces in FP64 registers (no two threads add into
-//      the same entry, no atomics touch S).
+//      (three rows each, sharing Z_b through a lane swap) sum the piece's -Z_a Z_b^T
+//      (lower triangle of Z_a Z_b^T + Z_b Z_a^T for two observations on one camera) in
+//      registers and write it to LDS in list order; 14 groups of 36 threads each own one
+//      entry of every 14th camera block and add up the contiguous run of their block's
+//      pieces in FP64 registers (no two threads add into the same entry, no atomics
+//      touch S).
 // At the end of the tile each owner writes its entry, plus the per-camera sums on the
 // diagonal blocks, to the tile's partial system; a separate kernel sums the partials of
 // a window in a fixed order (no global atomics).  The per-camera sums of step 2 are

@@ -1,7 +1,8 @@
 // Back-substitution, retraction and trial cost.
 //
-// One block per tile of points (same tiles as the linearisation).  The block forms the
-// trial poses Exp(dp_k) T_k of its window in LDS, then walks its points in chunks of
+// One block per part of a tile of points (the linearisation's tiles, each split into
+// `split` parts of about 512 points, in index order).  The block forms the trial poses
+// Exp(dp_k) T_k of its window in LDS, then walks its points in chunks of
 // whole points (one observation per lane).  Each lane forms W_a^T dp_k(a) = R^T G c in
 // FP64 at the current state (G = om P^T P, c the camera-frame motion of dp); the first
 // lane of each point sums them and back-substitutes with the point factor the
