@@ -58,22 +58,8 @@ __global__ __launch_bounds__(kCostThreads) void k_cost(CostArgs a) {
     if (BWD) cur += cost_align(sizeof(float) * kCostChunk * 3);
     double *red = reinterpret_cast<double *>(cur);
 
-    // poses Exp(xi_k) T_k, composed in FP64, used in FP32
-    for (int k = tid; k < K; k += kCostThreads) {
-        const double *T0 = a.T + (int64_t)(W.kf0 + k) * 12;
-        double Tk[12];
-        if (a.xi) {
-            double x[6];
-#pragma unroll
-            for (int q = 0; q < 6; ++q) x[q] = (double)a.xi[(int64_t)(W.kf0 + k) * 6 + q];
-            se3_left_update(x, T0, Tk);
-        } else {
-#pragma unroll
-            for (int i = 0; i < 12; ++i) Tk[i] = T0[i];
-        }
-#pragma unroll
-        for (int i = 0; i < 12; ++i) P[k * 12 + i] = (float)Tk[i];
-    }
+    // poses Exp(xi_k) T_k (formed in FP64 by the set-up kernel), used in FP32
+    for (int i = tid; i < 12 * K; i += kCostThreads) P[i] = a.Pf[(int64_t)W.kf0 * 12 + i];
     if (BWD)
         for (int i = tid; i < kCostWaves * K * 6; i += kCostThreads) gc[i] = 0.0;
     __syncthreads();
@@ -250,36 +236,64 @@ __device__ inline void se3_left_jacobian_t(const double *xi, const double *g, do
 }
 
 // per window: cost = sum of the tile costs; backward: pose gradients (all keyframes,
-// fixed or not) = J_l(xi)^T times the sum of the tile partials
+// fixed or not) = J_l(xi)^T times the sum of the tile partials.  Both sums run in a
+// fixed order: thread i adds the tiles i, i + G, ... (G threads per entry), then the
+// block adds the G partial sums in order.
+constexpr int kCostRedThreads = 256;
+
 template <bool BWD>
-__global__ void k_cost_reduce(CostArgs a, int n_windows) {
+__global__ __launch_bounds__(kCostRedThreads) void k_cost_reduce(CostArgs a, int n_windows) {
+    __shared__ double part[kCostRedThreads];
+    __shared__ double gsum[kMaxKf * 6];
     const int w = blockIdx.x;
     if (w >= n_windows) return;
     const CostWin W = a.win[w];
+    const int tid = threadIdx.x;
     if (!BWD) {
-        if (threadIdx.x == 0) {
-            double F = 0.0;
-            for (int t = 0; t < W.ntiles; ++t) F += a.partF[W.tile0 + t];
-            a.cost[w] = F;
+        double F = 0.0;
+        for (int t = tid; t < W.ntiles; t += kCostRedThreads) F += a.partF[W.tile0 + t];
+        part[tid] = F;
+        __syncthreads();
+        if (tid == 0) {
+            double s = 0.0;
+            for (int i = 0; i < kCostRedThreads; ++i) s += part[i];
+            a.cost[w] = s;
         }
         return;
     }
-    for (int k = threadIdx.x; k < W.K; k += blockDim.x) {
-        double g[6] = {0, 0, 0, 0, 0, 0};
-        for (int t = 0; t < W.ntiles; ++t) {
-            const double *src = a.partG + W.g_off + ((int64_t)t * W.K + k) * 6;
-#pragma unroll
-            for (int q = 0; q < 6; ++q) g[q] += src[q];
+    const int KE = W.K * 6;   // entries of the window's pose gradient (K <= kMaxKf)
+    const double *src = a.partG + W.g_off;
+    if (KE > 0 && KE <= kCostRedThreads) {   // G threads per entry, then G partials in order
+        const int G = kCostRedThreads / KE;
+        const int e = tid % KE, gi = tid / KE;
+        double g = 0.0;
+        if (gi < G)
+            for (int t = gi; t < W.ntiles; t += G) g += src[(int64_t)t * KE + e];
+        part[tid] = g;
+        __syncthreads();
+        if (tid < KE) {
+            double s = 0.0;
+            for (int q = 0; q < G; ++q) s += part[q * KE + tid];
+            gsum[tid] = s;
         }
+    } else {
+        for (int e = tid; e < KE; e += kCostRedThreads) {
+            double s = 0.0;
+            for (int t = 0; t < W.ntiles; ++t) s += src[(int64_t)t * KE + e];
+            gsum[e] = s;
+        }
+    }
+    __syncthreads();
+    for (int k = tid; k < W.K; k += kCostRedThreads) {
         double y[6];
         if (a.xi) {
             double x[6];
 #pragma unroll
             for (int q = 0; q < 6; ++q) x[q] = (double)a.xi[(int64_t)(W.kf0 + k) * 6 + q];
-            se3_left_jacobian_t(x, g, y);
+            se3_left_jacobian_t(x, gsum + 6 * k, y);
         } else {
 #pragma unroll
-            for (int q = 0; q < 6; ++q) y[q] = g[q];
+            for (int q = 0; q < 6; ++q) y[q] = gsum[6 * k + q];
         }
 #pragma unroll
         for (int q = 0; q < 6; ++q) a.g_xi[(int64_t)(W.kf0 + k) * 6 + q] = (float)y[q];
@@ -299,9 +313,9 @@ hipError_t launch_cost(const CostArgs &a, int ntiles, int max_k, bool backward, 
 hipError_t launch_cost_reduce(const CostArgs &a, int n_windows, bool backward, hipStream_t s) {
     if (n_windows <= 0) return hipSuccess;
     if (backward)
-        hipLaunchKernelGGL(k_cost_reduce<true>, dim3(n_windows), dim3(128), 0, s, a, n_windows);
+        hipLaunchKernelGGL(k_cost_reduce<true>, dim3(n_windows), dim3(kCostRedThreads), 0, s, a, n_windows);
     else
-        hipLaunchKernelGGL(k_cost_reduce<false>, dim3(n_windows), dim3(64), 0, s, a, n_windows);
+        hipLaunchKernelGGL(k_cost_reduce<false>, dim3(n_windows), dim3(kCostRedThreads), 0, s, a, n_windows);
     return hipGetLastError();
 }
 

@@ -20,8 +20,9 @@ enum : int32_t {
     ERR_TOO_MANY_OBS = 256, ERR_STEREO_NO_BASELINE = 512
 };
 
-// copy the inputs into the working state and reset the control blocks (each of these
-// steps is skipped when its destination is null), then the point -> observation offsets
+// copy the inputs into the working state, reset the control blocks and form the cost
+// layer's perturbed poses (each of these steps is skipped when its destination is null),
+// then the point -> observation offsets
 __global__ void k_setup(MiscArgs a) {
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nth = (int64_t)gridDim.x * blockDim.x;
@@ -29,6 +30,23 @@ __global__ void k_setup(MiscArgs a) {
         for (int64_t i = tid; i < (int64_t)a.n_kf * 12; i += nth) a.T[i] = a.T_in[i];
     if (a.X0)
         for (int64_t i = tid; i < (int64_t)a.n_pt * 3; i += nth) a.X0[i] = a.X_in[i];
+    // cost layer: the perturbed poses Exp(xi_k) T_k, composed in FP64 once per call and
+    // used in FP32 by every tile of the keyframe's window
+    for (int64_t k = tid; a.Pf && k < a.n_kf; k += nth) {
+        const double *T0 = a.T_in + k * 12;
+        double Tk[12];
+        if (a.xi) {
+            double x[6];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) x[q] = (double)a.xi[k * 6 + q];
+            se3_left_update(x, T0, Tk);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 12; ++i) Tk[i] = T0[i];
+        }
+#pragma unroll
+        for (int i = 0; i < 12; ++i) a.Pf[k * 12 + i] = (float)Tk[i];
+    }
     for (int64_t w = tid; a.ctl && w < a.c.n_windows; w += nth) {
         Ctl c;
         c.lambda = 0.0; c.nu = 2.0; c.F = 0.0; c.F_trial = 0.0; c.denom_p = 0.0;

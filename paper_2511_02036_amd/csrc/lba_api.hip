@@ -106,6 +106,18 @@ int choose_points_per_tile(const lba_options &opt, int64_t total_points) {
     return (int)p;
 }
 
+// The cost layer has no per-tile reduced system, so its tiles are small: about 448
+// observations each (two mostly full 256-observation chunks), which gives a few
+// thousand blocks over a batch.  Measured on 64 windows of 2,000 points and about 6.7
+// observations per point: tiles of 64 points beat 16, 24, 33, 48 and 128 (one chunk per
+// tile pays the block's fixed costs too often; four chunks leave too few blocks).
+int choose_cost_points_per_tile(const lba_options &opt, int64_t total_points, int64_t total_obs) {
+    if (opt.points_per_tile > 0) return opt.points_per_tile;
+    if (total_points <= 0 || total_obs <= 0) return 64;
+    int64_t p = (int64_t)(448.0 * (double)total_points / (double)total_obs);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(4096, p));
+}
+
 int kopt_class(int kopt) { return kopt <= 10 ? 0 : (kopt <= 20 ? 1 : 2); }
 
 void tune_signature(const lba_problem *P, int nw, bool mixed, int64_t *sig) {
@@ -777,7 +789,8 @@ struct CostPlan {
     std::vector<CostWin> win;
     std::vector<Tile> tiles;
     std::vector<int32_t> kf_off, pt_off, obs_off;
-    size_t o_win, o_tiles, o_kfoff, o_ptoff, o_obsoff, o_upload_end, o_ptstart, o_partF, o_partG, o_err, total;
+    size_t o_win, o_tiles, o_kfoff, o_ptoff, o_obsoff, o_upload_end, o_ptstart, o_partF, o_partG, o_pf, o_err,
+        total;
 };
 
 lba_status build_cost_plan(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, CostPlan &cp) {
@@ -813,7 +826,7 @@ lba_status build_cost_plan(lba_ctx *ctx, const lba_problem *P, const lba_batch *
     if (cp.kf_off[0] != 0 || cp.pt_off[0] != 0 || cp.obs_off[0] != 0 || cp.kf_off[nw] != P->n_kf ||
         cp.pt_off[nw] != P->n_pt || cp.obs_off[nw] != P->n_obs)
         return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "batch offsets must start at 0 and end at the totals");
-    const int ppt = choose_points_per_tile(ctx->opt, P->n_pt);
+    const int ppt = choose_cost_points_per_tile(ctx->opt, P->n_pt, P->n_obs);
     int64_t g = 0;
     cp.win.resize(nw);
     cp.tiles.clear();
@@ -856,6 +869,7 @@ lba_status build_cost_plan(lba_ctx *ctx, const lba_problem *P, const lba_batch *
     cp.o_ptstart = o; o = align256(o + sizeof(int32_t) * ((size_t)P->n_pt + 1));
     cp.o_partF = o;   o = align256(o + sizeof(double) * std::max<size_t>(cp.tiles.size(), 1));
     cp.o_partG = o;   o = align256(o + sizeof(double) * std::max<int64_t>(g, 1));
+    cp.o_pf = o;      o = align256(o + sizeof(float) * 12 * std::max<size_t>((size_t)P->n_kf, 1));
     cp.o_err = o;     o = align256(o + sizeof(int32_t) * 16);
     cp.total = o;
     return LBA_OK;
@@ -930,6 +944,8 @@ lba_status cost_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, boo
     m.n_levels = P->n_levels;
     m.c.cam = {P->cam.fx, P->cam.fy, P->cam.cx, P->cam.cy, P->cam.bf};
     m.c.n_windows = nw;
+    m.xi = xi;
+    m.Pf = static_cast<float *>(W_(cp.o_pf));
 
     HIPCHK(timed(ctx, LBA_KCLASS_SETUP, s, [&] { return launch_setup(m, nw, s); }));
     if (ctx->opt.check_inputs) {
@@ -949,6 +965,7 @@ lba_status cost_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, boo
     ca.pt_start = d_ptstart;
     ca.T = P->T_cw;
     ca.xi = xi;
+    ca.Pf = m.Pf;
     ca.X = X;
     ca.z = z;
     ca.obs_kf = P->obs_kf;

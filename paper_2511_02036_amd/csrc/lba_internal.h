@@ -198,6 +198,8 @@ struct MiscArgs {
     int32_t n_kf, n_pt, n_levels;
     int32_t round;
     int32_t count;               // k_flags: add the flagged observations to Ctl::n_outliers
+    const float *xi;             // cost layer: pose perturbations (n_kf x 6, or null: none)
+    float *Pf;                   // cost layer: Exp(xi_k) T_k in FP32 (n_kf x 12); null: skip
     SolveConsts c;
 };
 
@@ -214,6 +216,7 @@ struct CostArgs {
     const int32_t *pt_start;     // global point -> first global observation (n_pt + 1)
     const double *T;             // base poses, n_kf x 12
     const float *xi;             // left perturbations, n_kf x 6, or nullptr (zero)
+    const float *Pf;             // Exp(xi_k) T_k in FP32, n_kf x 12 (formed by k_setup)
     const float *X;              // points, n_pt x 3
     const float *z;              // measurements, 3 x n_obs planar
     const int32_t *obs_kf, *obs_pt;

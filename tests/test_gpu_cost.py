@@ -214,3 +214,34 @@ def test_invalid_index_is_rejected():
     X32, z32, _, tX, tz = _inputs(bad)
     with pytest.raises(lba.LBAError, match="keyframe index"):
         layer.forward(None, tX, tz)
+
+
+@pytest.mark.parametrize("points_per_tile", [0, 37])
+def test_many_keyframes_and_uneven_tiles(ref, points_per_tile):
+    """A batch of a 50-keyframe window (its 300 pose-gradient entries exceed one reduce
+    block, the per-entry path of the tile reduction) and a 5-keyframe window, at a
+    nonzero perturbation; the default tile size and a small one that leaves ragged last
+    tiles both match the oracle."""
+    from paper_2511_02036_amd import lba
+    rng = np.random.default_rng(21)
+    big = synth.make_window(rng, trajectory="walk", K=50, n_fixed=20, M=1500, nobs=(4, 10), stereo_p=0.7,
+                            walk_length=10.0)
+    small = synth.make_window(rng, trajectory="walk", K=5, n_fixed=1, M=300, nobs=(3, 5), stereo_p=0.0,
+                              walk_length=2.0)
+    cat = synth.concat([big, small])
+    xi = (rng.standard_normal((cat["T_cw"].shape[0], 6)) * 0.03).astype(np.float32)
+    ctx = lba.Context(device=0, points_per_tile=points_per_tile)
+    layer = lba.CostLayer(ctx, cat, device="cuda:0")
+    X32, z32, txi, tX, tz = _inputs(cat, xi)
+    cost = layer.forward(txi, tX, tz).cpu().numpy()
+    g = torch.tensor([0.5, -1.5], dtype=torch.float64, device="cuda:0")
+    gxi, gX, gz = [t.cpu().numpy() for t in layer.backward(txi, tX, tz, g)]
+    from tests.parity import window_slice
+    for i in range(2):
+        F, rgxi, rgX, rgz, _ = _oracle_window(ref, cat, i, X32, z32, xi32=xi)
+        ks, ps, os_ = window_slice(cat, i)
+        gi = float(g[i])
+        assert abs(cost[i] - F) <= 1e-5 * abs(F), (i, cost[i], F)
+        _close(gxi[ks], gi * rgxi, f"window {i} g_xi")
+        _close(gX[ps], gi * rgX, f"window {i} g_X")
+        _close(gz[:, os_], gi * rgz, f"window {i} g_z")
