@@ -53,6 +53,9 @@ struct LinCfg {
     static constexpr int PB = 256;                             // pieces per batch
     static constexpr int kPiece = sizeof(Real) == 4 ? 8 : 4;   // pairs per piece (measured best)
     static constexpr int PS = 37;                              // product row stride (odd)
+    // Z row stride in values: 19 (odd) rather than 18, so that the rows the lanes of a
+    // wavefront gather by pair start in twice as many distinct LDS banks
+    static constexpr int ZS = 19;
     static constexpr int RPT = 6 * PB / kNT;                   // product rows per thread
     static_assert(RPT == 3, "two neighbouring threads per piece");
     static_assert(PCAP < 65536, "packed scan of pair and piece counts");
@@ -62,7 +65,7 @@ template <typename Real>
 struct LinSmem {
     double *T;       // K x 12 poses
     int *opt;        // K
-    Real *Z;         // CO x 18
+    Real *Z;         // CO x ZS (18 values per observation)
     double *hs;      // CO x 9    FP64 Hll_a (6) and bl_a (3) for the point sums
     double *dacc;    // kMaxOpt x 27: per camera, sum of D_a (lower triangle, 21) and r_a (6)
     unsigned *pairs; // PCAP pairs, then PCAP + 1 piece starts (list positions)
@@ -111,7 +114,8 @@ __device__ __forceinline__ void piece_product(const LinSmem<Real> &sm, int r0, i
 #pragma unroll
         for (int u = 0; u < NP; ++u) {
             const Real wgt = r0 + u < r1 ? (Real)1 : (Real)0;
-            const Real *za = sm.Z + (e[u] & 1023) * 18 + R0 * 3, *zb = sm.Z + ((e[u] >> 10) & 1023) * 18 + R0 * 3;
+            constexpr int ZS = LinCfg<Real>::ZS;
+            const Real *za = sm.Z + (e[u] & 1023) * ZS + R0 * 3, *zb = sm.Z + ((e[u] >> 10) & 1023) * ZS + R0 * 3;
             Real ai[9], bh[9], bo[9];
 #pragma unroll
             for (int c = 0; c < 9; ++c) {
@@ -141,7 +145,7 @@ __device__ __forceinline__ void piece_product(const LinSmem<Real> &sm, int r0, i
         for (int c = 0; c < 18; ++c) acc[c] = (Real)0;
         for (int r = r0; r < r1; ++r) {
             const unsigned e = sm.pairs[r];
-            const Real *za = sm.Z + (e & 1023) * 18, *zb = sm.Z + ((e >> 10) & 1023) * 18;
+            const Real *za = sm.Z + (e & 1023) * LinCfg<Real>::ZS, *zb = sm.Z + ((e >> 10) & 1023) * LinCfg<Real>::ZS;
             Real ai[9], bi[9];
 #pragma unroll
             for (int c = 0; c < 9; ++c) {
@@ -175,7 +179,7 @@ __host__ __device__ inline size_t lin_carve(unsigned char *base, int K, LinSmem<
     auto take = [&](size_t bytes) { void *p = base ? (void *)(base + o) : nullptr; o = align_up(o + bytes, 16); return p; };
     void *T = take(sizeof(double) * 12 * K);
     void *opt = take(sizeof(int) * K);
-    void *Z = take(sizeof(Real) * C::CO * 18);
+    void *Z = take(sizeof(Real) * C::CO * C::ZS);
     // the staging of phases 1-2 (point-sum terms, then the chunk's point positions (512 x
     // 3), observation ranges (513), first observations and indices of its points (512
     // each) and the point of each observation slot (CO), see the kernel) and the piece
@@ -470,7 +474,7 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             bpd[2] = xc * gd[1] - yc * gd[0];
             bpd[3] = gd[0]; bpd[4] = gd[1]; bpd[5] = gd[2];
 #pragma unroll
-            for (int i = 0; i < 18; ++i) sm.Z[tid * 18 + i] = Zr[i];
+            for (int i = 0; i < 18; ++i) sm.Z[tid * C::ZS + i] = Zr[i];
             // the observation's own term, D_a = Hpp_a - Z_a Z_a^T and r_a = bp_a - Z_a t, goes
             // straight into its camera's LDS sums
             double *dst = sm.dacc + ka * 27;
