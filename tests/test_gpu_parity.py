@@ -171,3 +171,21 @@ def test_large_tiles_split_across_update_blocks(precision):
     else:
         from tests.parity import assert_mixed_tolerances
         assert_mixed_tolerances(w, g["T"], g["X"], g["stats"][0], r)
+
+
+def test_size_limits_are_rejected_before_any_solve():
+    """31 optimisable keyframes exceed the reduced system's limit of 30 (both
+    precisions); a point with 65 observations exceeds one wavefront.  Both are refused
+    with a message, and the largest accepted case (30) is solved by the C3 tests."""
+    w = synth.tiny_window(30, K=33, n_fixed=2, M=120, nobs=(3, 6), stereo_p=0.5)
+    for precision in ("fp64", "mixed"):
+        with pytest.raises(lba.LBAError, match="31 optimisable keyframes"):
+            _gpu(w, precision=precision)
+    w = synth.tiny_window(31, K=5, n_fixed=2, M=20, nobs=(2, 4), stereo_p=0.5)
+    first = np.flatnonzero(w["obs_pt"] == 0)[0]
+    rep = np.full(63, first)
+    idx = np.sort(np.concatenate([np.arange(len(w["obs_pt"])), rep]), kind="stable")
+    w = {k: (v[..., idx] if k.startswith("obs_") else v) for k, v in w.items()}
+    assert (w["obs_pt"] == 0).sum() > 64
+    with pytest.raises(lba.LBAError, match="invalid"):
+        _gpu(w)
