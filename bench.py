@@ -123,6 +123,28 @@ def kernel_bytes_and_flops(cls, s, n_tiles, real_bytes, z_bytes):
     return 0, 0
 
 
+def copy_peak_gbs(dev, mib=1024, reps=10):
+    """Device-to-device copy rate of this GPU (bytes read + written per second, best of
+    three timed groups of `reps` copies of `mib` MiB): the HBM rate a plain stream reaches
+    here, reported beside the published 8 TB/s."""
+    import torch
+    src = torch.empty(mib << 20, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = None
+    for _ in range(3):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            dst.copy_(src)
+        b.record()
+        b.synchronize()
+        t = a.elapsed_time(b) * 1e-3
+        best = t if best is None else min(best, t)
+    del src, dst
+    return 2.0 * (mib << 20) * reps / best / 1e9
+
+
 def kernel_roofs(cls, shapes, mean_us, mixed, z_f32):
     ppt = tile_points(sum(s["M"] for s in shapes))
     tb = tf = 0.0
@@ -254,6 +276,9 @@ def bench_cost_layer(args, spec):
     roof = dict(kernel="cost_backward", bound="hbm", achieved=b / mb / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=b / mb / 1e9 / HBM_PEAK_GBS, traffic=measured_traffic(args.workload, "cost_backward"), bytes_per_launch=b, mean_us=kern["cost_backward"]["mean_us"],
                 alu_TFLOPs=f / mb / 1e12)
+    cp = copy_peak_gbs(dev)
+    roof["copy_peak_GBs"] = cp
+    roof["frac_of_copy_peak"] = b / mb / 1e9 / cp
     nw = len(windows)
     out = {"metric": METRIC, "value": nw * steps / el, "unit": "window-cost-gradients/s", "n_gpus": 1,
            "steps": steps, "warmup": args.warmup, "ms_per_step": 1e3 * el / steps, "higher_is_better": True,
@@ -381,12 +406,15 @@ def main():
         roof = dict(kernel=dom, bound="hbm", achieved=r["achieved_GBs"], peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=r["hbm_frac"], traffic=traffic, bytes_per_launch=r["bytes_per_launch"],
                     mean_us=r["mean_us"], alu_TFLOPs=r["achieved_TFLOPs"], alu_frac=r["alu_frac"])
+    cp = copy_peak_gbs(dev)
+    roof["copy_peak_GBs"] = cp
+    roof["hbm_frac_of_copy_peak"] = r["achieved_GBs"] / cp
     streaming = {}
     for k in ("linearize", "update"):
         if kern[k]["launches"]:
             rk = kernel_roofs(k, shapes, kern[k]["mean_us"], mixed, z_f32)
             streaming[k] = {"mean_us": round(rk["mean_us"], 2), "GB/s": round(rk["achieved_GBs"], 1),
-                            "hbm_frac": round(rk["hbm_frac"], 4), "TFLOP/s": round(rk["achieved_TFLOPs"], 2),
+                            "hbm_frac": round(rk["hbm_frac"], 4), "frac_of_copy_peak": round(rk["achieved_GBs"] / cp, 4), "TFLOP/s": round(rk["achieved_TFLOPs"], 2),
                             "alu_frac": round(rk["alu_frac"], 4)}
 
     value = iters / el
