@@ -22,7 +22,8 @@
 //      its own; the threads of a point share its pairs round-robin (a chunk with two
 //      observations of one point on one camera falls back to LDS integer atomics);
 //   4. each block's run of the list is cut into pieces of at most kPiece pairs (8 in
-//      FP32, 4 in FP64); in batches of PB pieces, two neighbouring threads per piece
+//      FP32, or 6 when the chunk's pieces of 6 fit one batch; 4 in FP64); in batches of
+//      PB pieces, two neighbouring threads per piece
 //      (three rows each, sharing Z_b through a lane swap) sum the piece's -Z_a Z_b^T
 //      (lower triangle of Z_a Z_b^T + Z_b Z_a^T for two observations on one camera) in
 //      registers and write it to LDS in list order; 14 groups of 36 threads each own one
@@ -52,6 +53,9 @@ struct LinCfg {
     static constexpr int PCAP = sizeof(Real) == 4 ? 3072 : 2080;   // pairs per chunk (>= 64*65/2)
     static constexpr int PB = 256;                             // pieces per batch
     static constexpr int kPiece = sizeof(Real) == 4 ? 8 : 4;   // pairs per piece (measured best)
+    // FP32 chunks whose pieces of kPieceSmall pairs fit one batch use those instead: the
+    // batch then costs each lane kPieceSmall pair products rather than kPiece
+    static constexpr int kPieceSmall = sizeof(Real) == 4 ? 6 : 4;
     static constexpr int PS = 37;                              // product row stride (odd)
     // Z row stride in values: 19 (odd) rather than 18, so that the rows the lanes of a
     // wavefront gather by pair start in twice as many distinct LDS banks
@@ -100,11 +104,10 @@ __device__ __forceinline__ Real lane_pair_swap(Real v) {
 // rows 3h .. 3h + 2 of Z_a and Z_b and takes the other half of Z_b from its neighbour;
 // the list entries of the piece load at once and the pairs are unrolled without branches
 // (a missing pair repeats the last with weight 0).
-template <typename Real>
+template <typename Real, int NP>
 __device__ __forceinline__ void piece_product(const LinSmem<Real> &sm, int r0, int r1, int fl, int h, Real *out) {
     const int R0 = 3 * h, R1 = 3 - R0;   // own rows, the neighbour's rows
     if (fl == 0) {   // Z_a Z_b^T, camera of a before camera of b
-        constexpr int NP = LinCfg<Real>::kPiece;
         Real own[9], oth[9];   // [i][jj]: row R0 + i of the sum, column R0 + jj / R1 + jj
 #pragma unroll
         for (int c = 0; c < 9; ++c) own[c] = oth[c] = (Real)0;
@@ -264,6 +267,30 @@ __device__ __forceinline__ int block_inclusive_scan(int v, int *scan, int tid) {
         const int v = scan[w];
         add += w < wave ? v : 0;
     }
+    return x + add;
+}
+
+// inclusive scan of one unsigned value per thread over the block (512 threads), and the
+// block's total.  The caller places a barrier between this and the next writer of scan[].
+__device__ __forceinline__ unsigned block_inclusive_scan_total(unsigned v, int *scan, int tid, unsigned &total) {
+    const int lane = tid & 63, wave = tid >> 6;
+    unsigned x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    unsigned *sc = reinterpret_cast<unsigned *>(scan);
+    if (lane == 63) sc[wave] = x;
+    __syncthreads();
+    unsigned add = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kNT / 64; ++w) {
+        const unsigned u = sc[w];
+        add += w < wave ? u : 0u;
+        tot += u;
+    }
+    total = tot;
     return x + add;
 }
 
@@ -518,7 +545,31 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             }
         }
         __syncthreads();
-        {   // pair offsets (low half) and piece offsets (high half) in one scan
+        int kp = C::kPiece;   // pairs per piece in this chunk (the same in every thread)
+        if constexpr (C::kPieceSmall != C::kPiece) {
+            // pair offsets (bits 0-11, at most PCAP = 3072), piece offsets for kPieceSmall
+            // (bits 12-21) and for kPiece (bits 22-31) in one scan: a block of c pairs has
+            // at most c / kPiece + 1 pieces, so each piece field stays below
+            // PCAP / kPieceSmall + kMaxBlocks = 977 < 1024
+            static_assert(C::PCAP < 4096 && C::PCAP / C::kPieceSmall + kMaxBlocks < 1024, "scan fields");
+            const unsigned c = tid < nblk ? (unsigned)sm.cnt[tid] : 0u;
+            const unsigned v = c | (((c + C::kPieceSmall - 1) / C::kPieceSmall) << 12) |
+                               (((c + C::kPiece - 1) / C::kPiece) << 22);
+            unsigned tot;
+            const unsigned incl = block_inclusive_scan_total(v, sm.scan, tid, tot);
+            const bool small = ((tot >> 12) & 1023u) <= (unsigned)C::PB;
+            kp = small ? C::kPieceSmall : C::kPiece;
+            const int sh = small ? 12 : 22;
+            if (tid < nblk) {
+                sm.cnt[tid] = (int)((incl - v) & 4095u);
+                pco[tid] = (int)(((incl - v) >> sh) & 1023u);
+            }
+            if (tid == nblk - 1) {
+                sm.cnt[nblk] = (int)(incl & 4095u);
+                pco[nblk] = (int)((incl >> sh) & 1023u);
+                pcs[(incl >> sh) & 1023u] = incl & 4095u;
+            }
+        } else {   // pair offsets (low half) and piece offsets (high half) in one scan
             const int c = tid < nblk ? sm.cnt[tid] : 0;
             const int v = c | (((c + C::kPiece - 1) / C::kPiece) << 16);
             const int incl = block_inclusive_scan(v, sm.scan, tid);
@@ -544,7 +595,10 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             const unsigned fl = kA == kB ? 2u : 0u;
             const int pos = sm.cnt[B] + rk;
             sm.pairs[pos] = (unsigned)first | ((unsigned)second << 10) | (fl << 20);
-            if (C::kPiece > 1 && rk % C::kPiece == 0) pcs[pco[B] + rk / C::kPiece] = (unsigned)pos;
+            if (C::kPiece > 1) {
+                const int pq = kp == C::kPiece ? rk / C::kPiece : rk / C::kPieceSmall;
+                if (rk == pq * kp) pcs[pco[B] + pq] = (unsigned)pos;
+            }
         };
         if (!anydup) {
             if (has) {
@@ -597,7 +651,10 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
                             __hip_atomic_fetch_or(&touch[B % kGroups], 1ull << (B / kGroups), __ATOMIC_RELAXED,
                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
                     }
-                    piece_product<Real>(sm, r0, r1, fl, h, out);
+                    if (C::kPieceSmall == C::kPiece || kp == C::kPiece)
+                        piece_product<Real, C::kPiece>(sm, r0, r1, fl, h, out);
+                    else
+                        piece_product<Real, C::kPieceSmall>(sm, r0, r1, fl, h, out);
                 }
             }
             __syncthreads();
