@@ -2,11 +2,12 @@
 //
 // One block per part of a tile of points (the linearisation's tiles, each split into
 // `split` parts of about 512 points, in index order).  The block forms the trial poses
-// Exp(dp_k) T_k of its window in LDS, then walks its points in chunks of
-// whole points (one observation per lane).  Each lane forms W_a^T dp_k(a) = R^T G c in
-// FP64 at the current state (G = om P^T P, c the camera-frame motion of dp); the first
-// lane of each point sums them and back-substitutes with the point factor the
-// linearisation of the same step stored, V = L L^T, t = L^-1 bl:
+// Exp(dp_k) T_k of its window in LDS, then each wavefront walks its share of the points
+// in chunks of whole points (one observation per lane; the point ends of the next chunk
+// are loaded while the current one is processed).  Each lane forms W_a^T dp_k(a) =
+// R^T G c in FP64 at the current state (G = om P^T P, c the camera-frame motion of dp);
+// lane l then sums them for the chunk's point l and back-substitutes with the point
+// factor the linearisation of the same step stored, V = L L^T, t = L^-1 bl:
 //   dl_j = L^-T (t - L^-1 q_j),   q_j = sum_a W_a^T dp_k(a),   X'_j = X_j + dl_j,
 // then every lane evaluates its observation's robust cost at (T', X') in FP64.  The block
 // writes its trial cost and its part of the gain-ratio denominator,
@@ -120,12 +121,15 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(UpdArgs a) {
     double Ftr = 0.0, den = 0.0;
     int fail = 0;
 
+    // the point ends of the next chunk are loaded one chunk ahead: lane l holds the end
+    // of point p + l, and the chunk's base is the end of the point before it
+    int pend = wp0 + lane < wp1 ? a.pt_start[wp0 + lane + 1] : 0;
+    int base = wp0 < wp1 ? a.pt_start[wp0] : 0;
     for (int p = wp0; p < wp1;) {
-        const int base = a.pt_start[p];
         const int cand = p + lane;
         int ok = 0, e = 0;
         if (cand < wp1) {
-            e = a.pt_start[cand + 1] - base;
+            e = pend - base;
             ok = e <= kMaxObsPerPoint;
         }
         const int q = p + __popcll(__ballot(ok));
@@ -133,9 +137,11 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(UpdArgs a) {
             fail = 1;
             break;
         }
-        // the chunk's point ranges and positions into this wavefront's LDS rows, loaded
-        // together with the observations
         const int npts = q - p;
+        const int nbase = __shfl(pend, npts - 1, 64);   // end of point q - 1 = start of point q
+        pend = q + lane < wp1 ? a.pt_start[q + lane + 1] : 0;
+        // the chunk's point ranges, positions and point factors (lane l: point p + l),
+        // loaded together with the observations
         if (lane < npts) {
             pst[lane + 1] = e;
             xs[3 * lane] = Xs[3 * (int64_t)cand];
@@ -159,14 +165,12 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(UpdArgs a) {
         const int nob = pst[npts];
         const bool has = lane < nob;
 
-        int s0 = 0, s1 = 0, j = 0, pl = 0;
+        int j = 0, pl = 0;
         double qv[3] = {0, 0, 0};
         double X0 = 0, X1 = 0, X2 = 0;
         if (has) {
             j = W.pt0 + jl;
             pl = j - p;
-            s0 = pst[pl];
-            s1 = pst[pl + 1];
             const int ka = sm.opt[kl];
             X0 = xs[3 * pl];
             X1 = xs[3 * pl + 1];
@@ -187,15 +191,17 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(UpdArgs a) {
 #pragma unroll
         for (int i = 0; i < 3; ++i) stgd[lane * 3 + i] = qv[i];
         wave_sync();
-        // the first lane of each point back-substitutes with the point factor the
-        // linearisation of this step left behind, and publishes dl
-        if (has && lane == s0) {
+        // lane l back-substitutes point p + l with the point factor the linearisation of
+        // this step left behind, and publishes dl (points without observations keep their
+        // position)
+        if (lane < npts && pst[lane + 1] > pst[lane]) {
+            const int m0 = pst[lane], m1 = pst[lane + 1];
             double qs[3] = {0, 0, 0};
-            for (int m = s0; m < s1; ++m) {
+            for (int m = m0; m < m1; ++m) {
 #pragma unroll
                 for (int i = 0; i < 3; ++i) qs[i] += stgd[m * 3 + i];
             }
-            const double *f = a.pf + 12 * (int64_t)j;
+            const double *f = a.pf + 12 * (int64_t)(p + lane);
             const double L0 = f[0], L1 = f[1], L2 = f[2], L3 = f[3], L4 = f[4], L5 = f[5];
             const double t0 = f[6], t1 = f[7], t2 = f[8];
             const double b0 = f[9], b1 = f[10], b2 = f[11];
@@ -207,14 +213,11 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(UpdArgs a) {
             const double d2 = L5 * y2;
             // q^T V^-1 bl = (L^-1 q) . (L^-1 bl)
             const double dq = u0 * t0 + u1 * t1 + u2 * t2;
-            const int slot = j - p;
-            ps[slot * 4 + 0] = d0;
-            ps[slot * 4 + 1] = d1;
-            ps[slot * 4 + 2] = d2;
-            ps[slot * 4 + 3] = d0 * (lambda * d0 + b0) + d1 * (lambda * d1 + b1) + d2 * (lambda * d2 + b2) + dq;
-        }
-        // points of the chunk without observations keep their position
-        if (lane < npts && pst[lane + 1] == pst[lane]) {
+            ps[lane * 4 + 0] = d0;
+            ps[lane * 4 + 1] = d1;
+            ps[lane * 4 + 2] = d2;
+            ps[lane * 4 + 3] = d0 * (lambda * d0 + b0) + d1 * (lambda * d1 + b1) + d2 * (lambda * d2 + b2) + dq;
+        } else if (lane < npts) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) ps[lane * 4 + i] = 0.0;
         }
@@ -239,6 +242,7 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(UpdArgs a) {
         }
         wave_sync();
         p = q;
+        base = nbase;
     }
 
     Ftr = wave_sum(Ftr);
