@@ -183,11 +183,11 @@ __host__ __device__ inline size_t lin_carve(unsigned char *base, int K, LinSmem<
     void *T = take(sizeof(double) * 12 * K);
     void *opt = take(sizeof(int) * K);
     void *Z = take(sizeof(Real) * C::CO * C::ZS);
-    // the staging of phases 1-2 (point-sum terms, then the chunk's point positions (512 x
-    // 3), observation ranges (513), first observations and indices of its points (512
-    // each) and the point of each observation slot (CO), see the kernel) and the piece
-    // products of phase 4 share space
-    constexpr size_t kStage = sizeof(double) * (C::CO * 9 + kNT * 3) + sizeof(int) * (kNT + 1 + 2 * kNT + C::CO);
+    // the staging of phases 1-2 (point-sum terms, then the chunk's observation ranges
+    // (513), first observations and indices of its points (512 each) and the point of
+    // each observation slot (CO), see the kernel) and the piece products of phase 4 share
+    // space
+    constexpr size_t kStage = sizeof(double) * (C::CO * 9) + sizeof(int) * (kNT + 1 + 2 * kNT + C::CO);
     constexpr size_t kProd = sizeof(Real) * C::PB * C::PS;
     void *prod = take(kStage > kProd ? kStage : kProd);
     void *hs = prod;
@@ -308,8 +308,7 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
     LinSmem<Real> sm;
     lin_carve<Real>(smem, K, &sm);
     unsigned long long *const cm = sm.touch + 2 * kGroups;
-    double *const xs = sm.hs + C::CO * 9;               // chunk point positions
-    int *const pst = reinterpret_cast<int *>(xs + 3 * kNT);   // chunk-local observation starts
+    int *const pst = reinterpret_cast<int *>(sm.hs + C::CO * 9);   // chunk-local observation starts
     int *const gst = pst + kNT + 1;                     // place of each point's first observation
     int *const pid = gst + kNT;                         // global index of each point
     int *const seg = pid + kNT;                         // chunk point of each observation slot
@@ -349,6 +348,9 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
     double Facc = 0.0;
     int fail = 0;
 
+    // the point records of the next chunk are loaded one chunk ahead (thread t: point p + t)
+    int4 pin = make_int4(0, 0, 0, 0);
+    if (tile.p0 + tid < tile.p1) pin = a.pinfo[tile.p0 + tid];
     for (int p = tile.p0; p < tile.p1;) {
         // The thread index is re-derived per chunk behind an empty asm statement, so the
         // compiler recomputes the LDS addresses built from it inside the chunk instead of
@@ -360,10 +362,9 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
         const int cand = p + tid;
         int P = 0, ps = 0, m = 0, inrange = 0;
         if (cand < tile.p1) {
-            const int4 pi = a.pinfo[cand];
-            P = pi.x;
-            ps = pi.w;   // place of the point's first observation
-            m = pi.z;
+            P = pin.x;
+            ps = pin.w;   // place of the point's first observation
+            m = pin.z;
             inrange = 1;
         }
         // observations (high word) and pair slots (low word) up to and including this point
@@ -376,26 +377,31 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             fail = 1;
             break;
         }
-        // the chunk's point ranges, positions and observation slots go to LDS
+        pin = make_int4(0, 0, 0, 0);
+        if (q + tid < tile.p1) pin = a.pinfo[q + tid];
+        // the chunk's point ranges and observation slots go to LDS
         const int np = q - p;
         if (tid < np) {
             pst[tid + 1] = obs_incl;
             gst[tid] = ps;
             pid[tid] = P;
             for (int i = obs_incl - m; i < obs_incl; ++i) seg[i] = tid;
-            xs[3 * tid] = Xs[3 * (int64_t)P];
-            xs[3 * tid + 1] = Xs[3 * (int64_t)P + 1];
-            xs[3 * tid + 2] = Xs[3 * (int64_t)P + 2];
         }
         if (tid == 0) pst[0] = 0;
         int pl = 0, kl = 0, stereo = 0, oct = 0;
         bool act = false;
         double zu = 0, zv = 0, zr = 0;
+        double X0 = 0, X1 = 0, X2 = 0;
         __syncthreads();
         const bool has = tid < pst[np];
-        if (has) {   // observation slot tid: observation tid - pst[pl] of chunk point pl
+        if (has) {   // observation slot tid: observation tid - pst[pl] of chunk point pl, and
+                     // its point's position, loaded together
             pl = seg[tid];
             const int o = gst[pl] + tid - pst[pl];   // the chunk's places are contiguous
+            const int64_t Pg = pid[pl];
+            X0 = Xs[3 * Pg];
+            X1 = Xs[3 * Pg + 1];
+            X2 = Xs[3 * Pg + 2];
             kl = a.sobs.kf[o];
             act = !a.smask || !a.smask[o];
             stereo = a.sobs.type[o];
@@ -407,15 +413,12 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
         // (only the raw observation stays in registers across the point-sum barrier; the
         //  factored blocks are recomputed from it in phase 2)
         int s0 = 0, s1 = 0, ka = -1, dup = 0;
-        double X0 = 0, X1 = 0, X2 = 0, omd = 0.0;
+        double omd = 0.0;
         double rho = 0.0;
         if (has) {
             s0 = pst[pl];
             s1 = pst[pl + 1];
             ka = sm.opt[kl];
-            X0 = xs[3 * pl];
-            X1 = xs[3 * pl + 1];
-            X2 = xs[3 * pl + 2];
             const double *T = sm.T + kl * 12;
             double xc, yc, zc, eu, ev, er;
             const double e2 = residual(cam, T, X0, X1, X2, zu, zv, zr, stereo, xc, yc, zc, eu, ev, er);
