@@ -75,7 +75,8 @@ typedef struct {
     double chi2_stereo;      /* outlier threshold on s, stereo [7.815] */
     double tau;              /* initial damping factor [1e-5] */
     int32_t points_per_tile; /* 0: per window from lba_tune's table for this problem if it
-                                was tuned, else from the total point count; else fixed */
+                                was tuned, else from the total point count (cost layer:
+                                tiles of about 448 observations); else fixed */
     int32_t use_graphs;      /* 1: each LM step (five kernels over every window) is captured
                                 once into a HIP graph and replayed; kernels are launched one
                                 by one while profiling is enabled [1] */
