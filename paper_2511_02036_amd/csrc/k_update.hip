@@ -140,8 +140,8 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(UpdArgs a) {
         const int npts = q - p;
         const int nbase = __shfl(pend, npts - 1, 64);   // end of point q - 1 = start of point q
         pend = q + lane < wp1 ? a.pt_start[q + lane + 1] : 0;
-        // the chunk's point ranges, positions and point factors (lane l: point p + l),
-        // loaded together with the observations
+        // the chunk's point ranges and positions (lane l: point p + l) into this
+        // wavefront's LDS rows, loaded together with the observations
         if (lane < npts) {
             pst[lane + 1] = e;
             xs[3 * lane] = Xs[3 * (int64_t)cand];
