@@ -516,6 +516,26 @@ void lbaref_flags(const ref_problem *P, const ref_options *O, const double *T, c
     }
 }
 
+/* Damping at the start of a round: tau times the largest diagonal entry of the
+ * undamped Gauss-Newton matrix H over every variable, pose and point blocks alike
+ * (Madsen, Nielsen & Tingleff, "Methods for Non-Linear Least Squares Problems", 2004,
+ * Section 3.2, the initial mu of the Levenberg-Marquardt method). */
+double lbaref_initial_damping(double tau, double max_diag_H) { return tau * max_diag_H; }
+
+/* Nielsen's damping update after one trial (same reference, Section 3.2): an accepted
+ * step with gain ratio g scales lambda by max(1/3, 1 - (2g - 1)^3) and resets nu to 2;
+ * a rejected one multiplies lambda by nu and doubles nu. */
+void lbaref_damping_update(double gain, int accepted, double *lambda, double *nu) {
+    if (accepted) {
+        double f = 2.0 * gain - 1.0;
+        *lambda *= fmax(1.0 / 3.0, 1.0 - f * f * f);
+        *nu = 2.0;
+    } else {
+        *lambda *= *nu;
+        *nu *= 2.0;
+    }
+}
+
 /* one LM round; returns the number of completed (accepted) iterations; *terminated set
  * when max_trials consecutive rejections ended the round early */
 static int lm_round(const ref_problem *P, const ref_options *O, int round, int iters,
@@ -529,7 +549,7 @@ static int lm_round(const ref_problem *P, const ref_options *O, int round, int i
     double *X2 = (double *)malloc(sizeof(double) * (3 * B->M + 1));
     linearize(P, O, T, X, active, robust, B);
     double F = B->F;
-    double lambda = O->tau * B->maxdiag, nu = 2.0;
+    double lambda = lbaref_initial_damping(O->tau, B->maxdiag), nu = 2.0;
     int done = 0;
     *terminated = 0;
     for (int it = 0; it < iters; ++it) {
@@ -553,18 +573,14 @@ static int lm_round(const ref_problem *P, const ref_options *O, int round, int i
                 L->solve_ok = !fail; L->pad = 0;
                 L->lambda = lambda; L->F = F; L->F_trial = F2; L->gain = gain;
             }
+            lbaref_damping_update(gain, acc, &lambda, &nu);
             if (acc) {
                 memcpy(T, T2, sizeof(double) * 12 * B->K);
                 memcpy(X, X2, sizeof(double) * 3 * B->M);
                 F = F2;
-                double f = 2.0 * gain - 1.0;
-                lambda *= fmax(1.0 / 3.0, 1.0 - f * f * f);
-                nu = 2.0;
                 accepted = 1;
                 break;
             }
-            lambda *= nu;
-            nu *= 2.0;
         }
         if (!accepted) {
             *terminated = 1;

@@ -81,6 +81,9 @@ def _load(path: str):
     L.lbaref_dense_system.argtypes = [P, O, dp, dp, u8p, C.c_int, dp, dp]
     L.lbaref_cost_grad.argtypes = [P, O, dp, dp, dp, dp]
     L.lbaref_cost_grad.restype = C.c_double
+    L.lbaref_initial_damping.argtypes = [C.c_double, C.c_double]
+    L.lbaref_initial_damping.restype = C.c_double
+    L.lbaref_damping_update.argtypes = [C.c_double, C.c_int, dp, dp]
     return L
 
 
@@ -310,3 +313,14 @@ def cost_grad(w: dict, xi=None, **opts):
     F = lib().lbaref_cost_grad(C.byref(b.P), C.byref(O), _p(x, C.c_double),
                                _p(gxi, C.c_double), _p(gX, C.c_double), _p(gz, C.c_double))
     return F, gxi, gX, gz
+
+
+def initial_damping(tau: float, max_diag: float) -> float:
+    return lib().lbaref_initial_damping(tau, max_diag)
+
+
+def damping_update(gain: float, accepted: bool, lam: float, nu: float) -> tuple[float, float]:
+    """One application of the oracle's damping rule: returns (lambda', nu')."""
+    l, n = C.c_double(lam), C.c_double(nu)
+    lib().lbaref_damping_update(gain, int(accepted), C.byref(l), C.byref(n))
+    return l.value, n.value

@@ -228,10 +228,9 @@ def test_noise_free_converges_to_ground_truth(ref, maker):
     # uniform additive damping re-initialised at tau * max diag(H) damps the weakly
     # constrained far points hard, so the zero-cost optimum takes more than 5 + 10 steps
     r = ref.solve(w, iters_round2=40)
-    assert r["stats"]["F_final"] < 1e-9
-    np.testing.assert_allclose(r["T"], w["T_true"], atol=1e-8)
-    # points: converged cost 1e-9 px^2-weighted bounds position to well under 1 um
-    np.testing.assert_allclose(r["X"], w["X_true"], atol=1e-6)
+    assert r["stats"]["F_final"] <= 1e-12
+    np.testing.assert_allclose(r["T"], w["T_true"], rtol=0, atol=1e-9)
+    np.testing.assert_allclose(r["X"], w["X_true"], rtol=0, atol=1e-9)
     assert not r["outlier"].any()
     # close to the noise-free optimum the Gauss-Newton model is exact to second order,
     # so the predicted decrease d^T(lambda d + b) matches the actual one: gain -> 1
@@ -376,3 +375,100 @@ def test_cost_gradient_finite_differences(ref, xi_scale):
             wm["obs_z"] = w["obs_z"].copy(); wm["obs_z"][m, i] -= h
             fd = (ref.cost_grad(wp, xi)[0] - ref.cost_grad(wm, xi)[0]) / (2 * h)
             assert gz[m, i] == pytest.approx(fd, rel=1e-6, abs=1e-6 * np.abs(gz).max())
+
+
+# ---------------------------------------------------------------------------------------
+# the damping schedule (Madsen, Nielsen & Tingleff 2004, Section 3.2)
+# ---------------------------------------------------------------------------------------
+def test_damping_update_golden(ref):
+    """Nielsen's update against values worked by hand (tests/golden/damping_cases.txt)."""
+    for lam, nu, gain, acc, want_lam, want_nu in _load("damping_cases.txt"):
+        got_lam, got_nu = ref.damping_update(gain, bool(acc), lam, nu)
+        assert got_lam == pytest.approx(want_lam, rel=1e-14, abs=1e-300), (lam, nu, gain, acc)
+        assert got_nu == want_nu, (lam, nu, gain, acc)
+
+
+def _max_diag(ref, w, T, X, active, robust):
+    H, _ = ref.dense_system(w, T=T, X=X, active=active, robust=robust)
+    return float(np.diag(H).max()) if H.size else 0.0
+
+
+@pytest.mark.parametrize("case", ["posed", "points_only", "round2_plain"])
+def test_initial_damping_each_round(ref, case):
+    """The first trial of each round uses lambda0 = tau * max diag(H) of the undamped dense
+    Gauss-Newton matrix over every variable at the state the round starts from (round 1:
+    the input; round 2: the end of round 1 on its inliers)."""
+    if case == "points_only":
+        w = synth.tiny_window(8, K=5, n_fixed=5, M=20, outlier_frac=0.2)
+    else:
+        w = synth.tiny_window(9, K=4, n_fixed=1, M=16, outlier_frac=0.2)
+    robust2 = 0 if case == "round2_plain" else 1
+    tau = 3e-4
+    full = ref.solve(w, tau=tau, round2_robust=robust2)
+    r1 = [l for l in full["log"] if l["round"] == 1]
+    r2 = [l for l in full["log"] if l["round"] == 2]
+    want1 = tau * _max_diag(ref, w, w["T_cw"], w["X"], None, True)
+    assert r1[0]["lam"] == pytest.approx(want1, rel=1e-12)
+    # the state at the end of round 1 and its outlier flags
+    end1 = ref.solve(w, tau=tau, iters_round2=0)
+    active = (~end1["outlier"]).astype(np.uint8)
+    want2 = tau * _max_diag(ref, w, end1["T"], end1["X"], active, bool(robust2))
+    assert r2 and r2[0]["lam"] == pytest.approx(want2, rel=1e-12)
+    # round 1 ended with a smaller lambda than round 2 restarts from: re-initialised
+    assert r2[0]["lam"] != r1[-1]["lam"]
+
+
+@pytest.mark.parametrize("maker", [synth.c1_mono, synth.c2_stereo])
+def test_damping_follows_the_rule_between_trials(ref, maker):
+    """Every trial's lambda follows from the previous trial of its round by the damping
+    rule (pinned above by hand-worked values), with nu reset by every acceptance."""
+    w = maker()
+    r = ref.solve(w)
+    for rnd in (1, 2):
+        recs = [l for l in r["log"] if l["round"] == rnd]
+        nu = 2.0
+        for a, b in zip(recs, recs[1:]):
+            lam, nu = ref.damping_update(a["gain"], a["accepted"], a["lam"], nu)
+            assert b["lam"] == pytest.approx(lam, rel=1e-15), (rnd, a, b)
+
+
+def test_rejections_end_round_after_max_trials(ref):
+    """tau = 0 and an optimisable keyframe that observes nothing: lambda0 = 0 stays 0 under
+    every rejection, the reduced matrix keeps a zero block, so every trial fails.  Each
+    round then ends after exactly max_trials trials with the state untouched."""
+    w = synth.tiny_window(10, K=4, n_fixed=1, M=15)
+    keep = w["obs_kf"] != 3                      # keyframe 3 (optimisable) sees nothing
+    for key in ("obs_kf", "obs_pt", "obs_type", "obs_oct"):
+        w[key] = w[key][keep]
+    w["obs_z"] = w["obs_z"][:, keep]
+    for mt in (1, 3, 10):
+        r = ref.solve(w, tau=0.0, max_trials=mt)
+        st = r["stats"]
+        assert st["trials"] == 2 * mt
+        assert st["iters_r1"] == 0 and st["iters_r2"] == 0
+        assert st["term_r1"] == 1 and st["term_r2"] == 1
+        assert st["lambda"] == 0.0
+        np.testing.assert_array_equal(r["T"], w["T_cw"])
+        np.testing.assert_array_equal(r["X"], w["X"])
+        assert len(r["log"]) == 2 * mt
+        assert all(not l["solve_ok"] and not l["accepted"] for l in r["log"])
+        assert [l["trial"] for l in r["log"]] == list(range(mt)) * 2
+
+
+@pytest.mark.parametrize("maker", [synth.c1_mono, synth.c2_stereo])
+def test_single_trial_budget(ref, maker):
+    """max_trials = 1: every iteration has one trial and the first rejection ends its
+    round, so each round's log is a run of acceptances, then at most one rejection."""
+    w = maker()
+    r = ref.solve(w, max_trials=1)
+    st = r["stats"]
+    for rnd, iters, term in ((1, 5, "term_r1"), (2, 10, "term_r2")):
+        recs = [l for l in r["log"] if l["round"] == rnd]
+        acc = [l["accepted"] for l in recs]
+        assert all(l["trial"] == 0 for l in recs)
+        n_acc = sum(acc)
+        assert acc == [True] * n_acc + [False] * (len(acc) - n_acc)
+        assert len(acc) - n_acc <= 1
+        assert st[term] == (1 if len(acc) > n_acc else 0)
+        assert n_acc == st["iters_r%d" % rnd] and (st[term] == 1 or n_acc == iters)
+    assert st["trials"] == len(r["log"])

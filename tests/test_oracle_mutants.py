@@ -53,13 +53,44 @@ MUTANTS = [
     ("grad_z_sign", "g_z[q * P->n_obs + i] = q < r ? 2.0 * om * e[q] : 0.0;",
      "g_z[q * P->n_obs + i] = q < r ? -2.0 * om * e[q] : 0.0;",
      [lambda: pins.test_cost_gradient_finite_differences(lbaref, 0.0)]),
+    # the damping schedule
+    ("nielsen_square_not_cube", "*lambda *= fmax(1.0 / 3.0, 1.0 - f * f * f);",
+     "*lambda *= fmax(1.0 / 3.0, 1.0 - f * f);",
+     [lambda: pins.test_damping_update_golden(lbaref)]),
+    ("nu_not_reset_on_accept", "        *nu = 2.0;\n    } else {", "        (void)0;\n    } else {",
+     [lambda: pins.test_damping_update_golden(lbaref)]),
+    ("reject_times_three", "*lambda *= *nu;", "*lambda *= 3.0;",
+     [lambda: pins.test_damping_update_golden(lbaref)]),
+    ("lambda0_pose_blocks_only", "for (int a = 0; a < 3; ++a) md = fmax(md, B->Hll[j * 9 + a * 4]);",
+     "for (int a = 0; a < 3; ++a) md = fmax(md, 0.0 * B->Hll[j * 9 + a * 4]);",
+     [lambda: pins.test_initial_damping_each_round(lbaref, "points_only")]),
+    ("no_round2_reinit",
+     [("double lambda = lbaref_initial_damping(O->tau, B->maxdiag), nu = 2.0;",
+       "static double carry = -1.0;\n    double lambda = (round == 2 && carry >= 0.0) ? carry : "
+       "lbaref_initial_damping(O->tau, B->maxdiag), nu = 2.0;"),
+      ("*lambda_out = lambda;", "*lambda_out = lambda;\n    carry = lambda;")],
+     None,
+     [lambda: pins.test_initial_damping_each_round(lbaref, "posed")]),
+    ("termination_off_by_one", "for (int trial = 0; trial < O->max_trials; ++trial) {",
+     "for (int trial = 0; trial <= O->max_trials; ++trial) {",
+     [lambda: pins.test_rejections_end_round_after_max_trials(lbaref)]),
 ]
+
+
+def _plant(name, orig, planted):
+    """The oracle source with one mistake planted: `orig` is one anchor text replaced by
+    `planted`, or a list of (anchor, replacement) pairs applied together."""
+    edits = orig if isinstance(orig, list) else [(orig, planted)]
+    src = SRC
+    for a, b in edits:
+        assert src.count(a) == 1, f"mutation anchor for {name} not unique in the oracle source"
+        src = src.replace(a, b)
+    return src
 
 
 @pytest.mark.parametrize("name,orig,planted,checks", MUTANTS, ids=[m[0] for m in MUTANTS])
 def test_planted_mistake_is_caught(tmp_path, name, orig, planted, checks):
-    assert SRC.count(orig) == 1, f"mutation anchor for {name} not unique in the oracle source"
-    path = lbaref.build_variant(SRC.replace(orig, planted), str(tmp_path / f"mut_{name}.so"))
+    path = lbaref.build_variant(_plant(name, orig, planted), str(tmp_path / f"mut_{name}.so"))
     caught = False
     with lbaref.use_library(path):
         for chk in checks:
