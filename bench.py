@@ -31,9 +31,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Local BA LM iter/s + residual/Hessian HBM GB/s; FP32/batched vs FP64 plain"
 HBM_PEAK_GBS = 8000.0
-# vector FMA peak of 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz; the library is built
-# without packed FP32 instructions, so FP32 and FP64 code share this roof
-VALU_PEAK_TFLOPS = 78.6
+# published MI355X vector peaks: FP32 157.3 TFLOP/s (256 CUs x 2.4 GHz x 256 flop/clock,
+# which needs packed FP32 FMAs) and FP64 78.6 TFLOP/s.  The library is built without packed
+# FP32 instructions, so its FP32 code issues at the FP64 / non-packed rate of 78.6; that
+# figure is reported beside the published one.
+FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
+NONPACKED_PEAK_TFLOPS = 78.6
 
 WORKLOADS = {
     "c5_batched_mixed": dict(
@@ -81,45 +85,40 @@ def make_windows(name):
     raise ValueError(name)
 
 
-def tile_points(total_points):
-    """Points per tile as the library's planner picks them by default."""
-    p = (total_points + 1023) // 1024
-    p = (p + 31) // 32 * 32
-    return max(64, min(4096, p))
-
-
 def window_shape(w):
     import numpy as np
     opt = w["fixed"] == 0
     on_opt = opt[w["obs_kf"]]
     cnt = np.bincount(w["obs_pt"][on_opt], minlength=len(w["X"]))
+    st = np.asarray(w["obs_type"]).astype(bool)
     return dict(K=len(w["fixed"]), M=len(w["X"]), N=len(w["obs_kf"]), Kopt=int(opt.sum()),
-                pairs=int((cnt * cnt).sum()))
+                N_stereo=int(st.sum()), pairs=int((cnt * (cnt - 1) // 2).sum()), self_terms=int(cnt.sum()))
 
 
-def kernel_bytes_and_flops(cls, s, n_tiles, real_bytes, z_bytes):
+# Algorithmic work per unit, from the scope table's measurement section (per observation
+# per LM step, FP32 bulk): the observation record is 22 B (u, v, uR 12 + keyframe 4 +
+# point 4 + octave 1 + type 1; 34 B with FP64 measurements); residual + Jacobian + block
+# Hessian 300 flops (mono) / 420 (stereo); the Schur complement 440 flops; the trial cost
+# 40.  A point's FP64 position is 24 B, read once per linearisation and read + written
+# once per update.
+FLOP_RES_HESS = {False: 300, True: 420}
+FLOP_SCHUR = 440
+FLOP_TRIAL = 40
+
+
+def kernel_bytes_and_flops(cls, s, z_bytes):
     """Algorithmic bytes and flops of ONE launch of a kernel class over one window of
-    shape s.  Bytes: what the kernel must read and write once (observation records,
-    point states, poses, its outputs).  Flops: counted from the formulas the kernel
-    evaluates (residual + Jacobian + blocks ~420 per observation, point factor ~60 per
-    point, 216 per ordered pair of a point's observations on optimisable keyframes; the
-    update kernel ~150 per observation and ~60 per point)."""
-    K, M, N, n = s["K"], s["M"], s["N"], 6 * s["Kopt"]
-    E = n * (n + 1) // 2
-    obs_rec = 4 + 4 + 3 * z_bytes + 1 + 1          # kf, pt, u/v/uR, type, octave
+    shape s: the per-unit figures above times the observations and points one launch
+    processes (every observation of the window: the masked round-2 outliers are read too)."""
+    M, N, Ns = s["M"], s["N"], s["N_stereo"]
+    obs_rec = 4 + 4 + 3 * z_bytes + 1 + 1
+    res_hess = FLOP_RES_HESS[False] * (N - Ns) + FLOP_RES_HESS[True] * Ns
     if cls == "linearize":
-        # + the point factor (96 B) each point leaves for the update kernel
-        b = N * obs_rec + M * (24 + 4 + 96) + n_tiles * (K * 100 + (E + 2 * n) * real_bytes + 32)
-        return b, 420 * N + 60 * M + 216 * s["pairs"]
+        return N * obs_rec + M * 24, res_hess + FLOP_SCHUR * N
     if cls == "update":
-        b = N * obs_rec + M * (24 + 24 + 4 + 96) + n_tiles * (K * 100 + n * 8 + 32)
-        return b, 150 * N + 60 * M
-    if cls == "reduce":
-        return n_tiles * (E + 2 * n) * real_bytes + (E + 2 * n) * 8, n_tiles * (E + 2 * n)
-    if cls == "cholesky":
-        return (E + 2 * n) * 8 + n * 8, n ** 3 / 3 + 2 * n * n
+        return N * obs_rec + M * 48, FLOP_TRIAL * N
     if cls == "linearize_init":
-        return N * obs_rec + M * 28, 300 * N
+        return N * obs_rec + M * 24, res_hess
     return 0, 0
 
 
@@ -146,17 +145,28 @@ def copy_peak_gbs(dev, mib=1024, reps=10):
 
 
 def kernel_roofs(cls, shapes, mean_us, mixed, z_f32):
-    ppt = tile_points(sum(s["M"] for s in shapes))
     tb = tf = 0.0
     for s in shapes:
-        b, f = kernel_bytes_and_flops(cls, s, (s["M"] + ppt - 1) // ppt, 4 if mixed else 8, 4 if z_f32 else 8)
+        b, f = kernel_bytes_and_flops(cls, s, 4 if z_f32 else 8)
         tb += b
         tf += f
     sec = mean_us * 1e-6
     gbs = tb / sec / 1e9 if sec > 0 else 0.0
     tfs = tf / sec / 1e12 if sec > 0 else 0.0
+    peak = FP32_PEAK_TFLOPS if mixed else FP64_PEAK_TFLOPS
     return dict(bytes_per_launch=tb, flops_per_launch=tf, mean_us=mean_us, achieved_GBs=gbs,
-                hbm_frac=gbs / HBM_PEAK_GBS, achieved_TFLOPs=tfs, alu_frac=tfs / VALU_PEAK_TFLOPS)
+                hbm_frac=gbs / HBM_PEAK_GBS, achieved_TFLOPs=tfs, alu_peak=peak, alu_frac=tfs / peak,
+                alu_frac_nonpacked=tfs / NONPACKED_PEAK_TFLOPS)
+
+
+def code_text(path):
+    """A source file with its comments and blank lines removed, each line stripped: the
+    key of a counter record, so that comment edits do not retire measured traffic."""
+    import re
+    src = open(path).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    return "\n".join(l.strip() for l in src.splitlines() if l.strip())
 
 
 def measured_traffic(workload, kernel):
@@ -169,23 +179,52 @@ def measured_traffic(workload, kernel):
     path = os.path.join(ROOT, "profiles", f"{workload}_traffic.md")
     if src is None or not os.path.exists(path):
         return None
-    with open(os.path.join(ROOT, "paper_2511_02036_amd", "csrc", src), "rb") as f:
-        h = hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256(code_text(os.path.join(ROOT, "paper_2511_02036_amd", "csrc", src)).encode()).hexdigest()[:16]
     with open(path) as f:
         for line in f:
             w = line.split()
-            if len(w) == 5 and w[0] == "traffic" and w[1] == "k_" + kernel and w[3] == "source-sha256":
+            if len(w) == 5 and w[0] == "traffic" and w[1] == "k_" + kernel and w[3] == "code-sha256":
                 return float(w[2]) if w[4] == h else None
     return None
 
 
-def cpu_baseline(windows, budget_s=12.0):
-    """The FP64 CPU oracle on a bounded sample of the workload's windows (a thread pool over
-    the host cores for batches, one thread for a single window).  Returns the baseline
-    record and {window index: oracle result} of the windows it solved."""
+def host_description():
+    """CPU model, logical CPUs of the host (nproc) and CPUs this process may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except AttributeError:
+        allowed = os.cpu_count() or 1
+    return dict(cpu_model=model, nproc=os.cpu_count() or 1, cpus_allowed=allowed)
+
+
+# threads of the oracle pool: the host's CPUs, at most 16 (the CPU share of one GPU on
+# the hosts this runs on)
+MAX_POOL = 16
+
+
+def cpu_baseline(windows, budget_s=12.0, single_budget_s=8.0, z_f32=False):
+    """The FP64 CPU oracle on a bounded sample of the workload's windows: a thread pool
+    over the host cores for batches (plus a one-thread figure on the first windows), one
+    thread for a single window.  Returns the baseline record and {window index: oracle
+    result} of the windows the pool solved."""
     from concurrent.futures import ThreadPoolExecutor
 
     from oracle import lbaref
+    host = host_description()
+    if z_f32:
+        # the oracle reads the measurements the GPU read (FP32-rounded), so that its results
+        # double as the parity reference of the benchmarked solve
+        from tests.parity import round_z_f32
+        windows = [round_z_f32(w) for w in windows]
     if len(windows) == 1:
         t0 = time.perf_counter()
         iters = runs = 0
@@ -198,8 +237,9 @@ def cpu_baseline(windows, budget_s=12.0):
             if el >= budget_s:
                 break
         return dict(value=iters / el, unit="window-LM-iterations/s", cores=1, kind="oracle",
-                    sample=f"{runs} full solves of the benchmark window in {el:.1f} s, one thread"), {0: last}
-    cores = max(1, min(16, os.cpu_count() or 1))
+                    sample=f"{runs} full solves of the benchmark window in {el:.1f} s, one thread",
+                    **host), {0: last}
+    cores = max(1, min(MAX_POOL, host["cpus_allowed"]))
     # estimate per-window cost from observation counts; take windows in batch order until
     # about budget_s of CPU time on the pool
     per_obs_s = 4.5e-6
@@ -215,9 +255,21 @@ def cpu_baseline(windows, budget_s=12.0):
     el = time.perf_counter() - t0
     iters = sum(int(r["stats"]["iters_r1"] + r["stats"]["iters_r2"]) for r in res)
     nobs = sum(len(windows[i]["obs_kf"]) for i in sample)
+    # one thread on the first windows of the batch, about single_budget_s
+    t1 = time.perf_counter()
+    it1 = n1 = ob1 = 0
+    while n1 < len(windows) and time.perf_counter() - t1 < single_budget_s:
+        r = lbaref.solve(windows[n1])
+        it1 += int(r["stats"]["iters_r1"] + r["stats"]["iters_r2"])
+        ob1 += len(windows[n1]["obs_kf"])
+        n1 += 1
+    el1 = time.perf_counter() - t1
     return dict(value=iters / el, unit="window-LM-iterations/s", cores=cores, kind="oracle",
                 sample=f"first {n} of {len(windows)} windows ({nobs} observations), one window per "
-                       f"thread on {cores} threads, {el:.1f} s"), dict(zip(sample, res))
+                       f"thread on {cores} threads, {el:.1f} s",
+                one_core=dict(value=it1 / el1, sample=f"first {n1} windows ({ob1} observations) in "
+                                                      f"{el1:.1f} s on one thread"),
+                **host), dict(zip(sample, res))
 
 
 def cost_layer_bytes(cls, windows):
@@ -398,14 +450,17 @@ def main():
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
     r = kernel_roofs(dom, shapes, kern[dom]["mean_us"], mixed, z_f32)
     traffic = measured_traffic(args.workload, dom)
+    common = dict(kernel=dom, traffic=traffic, flops_per_launch=r["flops_per_launch"],
+                  bytes_per_launch=r["bytes_per_launch"], mean_us=r["mean_us"],
+                  alu_TFLOPs=r["achieved_TFLOPs"], alu_frac=r["alu_frac"],
+                  alu_frac_of_nonpacked_78_6=r["alu_frac_nonpacked"], hbm_GBs=r["achieved_GBs"],
+                  hbm_frac=r["hbm_frac"])
     if r["alu_frac"] >= r["hbm_frac"]:
-        roof = dict(kernel=dom, bound="alu", achieved=r["achieved_TFLOPs"], peak=VALU_PEAK_TFLOPS,
-                    unit="TFLOP/s", frac=r["alu_frac"], traffic=traffic, flops_per_launch=r["flops_per_launch"],
-                    mean_us=r["mean_us"], hbm_GBs=r["achieved_GBs"], hbm_frac=r["hbm_frac"])
+        roof = dict(bound="alu", achieved=r["achieved_TFLOPs"], peak=r["alu_peak"], unit="TFLOP/s",
+                    frac=r["alu_frac"], **common)
     else:
-        roof = dict(kernel=dom, bound="hbm", achieved=r["achieved_GBs"], peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=r["hbm_frac"], traffic=traffic, bytes_per_launch=r["bytes_per_launch"],
-                    mean_us=r["mean_us"], alu_TFLOPs=r["achieved_TFLOPs"], alu_frac=r["alu_frac"])
+        roof = dict(bound="hbm", achieved=r["achieved_GBs"], peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=r["hbm_frac"], **common)
     cp = copy_peak_gbs(dev)
     roof["copy_peak_GBs"] = cp
     roof["hbm_frac_of_copy_peak"] = r["achieved_GBs"] / cp
@@ -465,12 +520,22 @@ def main():
         del solvers
 
     if not args.no_cpu_baseline:
-        cb, refs = cpu_baseline(windows)
+        cb, refs = cpu_baseline(windows, z_f32=z_f32)
         out["cpu_baseline"] = cb
-        # the oracle runs double as a parity spot check of the benchmarked solve
-        rel = [abs(solver.stats[i, 1] - r["stats"]["F_final"]) / abs(r["stats"]["F_final"]) for i, r in refs.items()]
-        out["parity_final_cost_rel_max"] = float(max(rel))
-        out["parity_windows_checked"] = len(rel)
+        # parity spot check of the benchmarked solve: the oracle on the same (FP32-rounded
+        # where the GPU read FP32) measurements, final cost and RMS reprojection difference
+        from tests.parity import reprojection_rms_diff, round_z_f32
+        T_out, X_out = solver.T_out.cpu().numpy(), solver.X_out.cpu().numpy()
+        rel, px = [], []
+        for i, r in refs.items():
+            w = round_z_f32(windows[i]) if z_f32 else windows[i]
+            k0, k1 = prob.kf_off[i], prob.kf_off[i + 1]
+            p0, p1 = prob.pt_off[i], prob.pt_off[i + 1]
+            rel.append(abs(solver.stats[i, 1] - r["stats"]["F_final"]) / abs(r["stats"]["F_final"]))
+            px.append(reprojection_rms_diff(w, T_out[k0:k1], X_out[p0:p1], r["T"], r["X"], ~r["outlier"]))
+        out["parity"] = {"windows_checked": len(rel), "final_cost_rel_max": float(max(rel)),
+                         "rms_reprojection_diff_px_max": float(max(px)),
+                         "oracle_inputs": "FP32-rounded measurements" if z_f32 else "FP64 measurements"}
     print(json.dumps(out), flush=True)
 
 

@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define LBA_ABI_VERSION 1
+#define LBA_ABI_VERSION 2
 
 typedef enum {
     LBA_OK = 0,
@@ -80,6 +80,8 @@ typedef struct {
     int32_t use_graphs;      /* 1: each LM step (five kernels over every window) is captured
                                 once into a HIP graph and replayed; kernels are launched one
                                 by one while profiling is enabled [1] */
+    int32_t trial_log;       /* records per window of the per-trial log kept in the workspace
+                                and returned through lba_result.log, 0..4096 [0] */
 } lba_options;
 
 typedef struct {
@@ -138,11 +140,25 @@ enum {
     LBA_STATS_LEN = 12
 };
 
+/* One damped solve of the LM loop (a trial), as the per-window decision records it:
+ * the round (1, 2), the iteration within the round (accepted steps so far), the trial
+ * within the iteration, whether it was accepted, whether the reduced system and every
+ * point block factorised, the damping it was solved with, the cost before it, the cost
+ * at the trial state and the gain ratio (F_trial and gain are not meaningful when
+ * solve_ok is 0). */
+typedef struct {
+    int32_t round, iter, trial, accepted, solve_ok, reserved;
+    double lambda, F, F_trial, gain;
+} lba_trial_record;
+
 typedef struct {
     double *T_out;       /* DEVICE n_kf x 12; may alias lba_problem.T_cw */
     double *X_out;       /* DEVICE n_pt x 3;  may alias lba_problem.X_w */
     uint8_t *outlier;    /* DEVICE n_obs, 1 = outlier at the final state */
     double *stats;       /* HOST n_windows x LBA_STATS_LEN, or NULL */
+    lba_trial_record *log;   /* HOST n_windows x options.trial_log records, or NULL: window w's
+                                first min(trials, trial_log) trials in order, from record
+                                w * trial_log on (trials = its LBA_STAT_TRIALS) */
 } lba_result;
 
 typedef struct lba_ctx lba_ctx;

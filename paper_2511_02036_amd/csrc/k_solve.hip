@@ -339,6 +339,19 @@ __global__ __launch_bounds__(64) void k_decide(DecideArgs a) {
         const int ok = ctl->solve_ok && fl == 0.0;
         const double gain = (ctl->F - Ft) / den;
         const int acc = ok && isfinite(Ft) && isfinite(gain) && gain > 0.0;
+        if (a.log && ctl->trials_total < a.log_cap) {
+            TrialRec &L = a.log[(int64_t)w * a.log_cap + ctl->trials_total];
+            L.round = a.round;
+            L.iter = ctl->iter;
+            L.trial = ctl->trial;
+            L.accepted = acc;
+            L.solve_ok = ok;
+            L.pad = 0;
+            L.lambda = ctl->lambda;
+            L.F = ctl->F;
+            L.F_trial = Ft;
+            L.gain = gain;
+        }
         ctl->F_trial = Ft;
         ctl->trials_total += 1;
         const int iters = a.c.iters[a.round - 1];

@@ -17,6 +17,8 @@
 
 using namespace lba;
 
+static_assert(sizeof(TrialRec) == sizeof(lba_trial_record), "trial record layout");
+
 struct lba_ctx {
     lba_options opt;
     int device = 0;
@@ -92,7 +94,8 @@ struct Plan {
     // workspace byte offsets
     size_t o_win, o_tiles, o_order, o_opt, o_kfoff, o_ptoff, o_obsoff, o_upload_end;
     size_t o_ptstart, o_ctl, o_T, o_X0, o_X1, o_part, o_partr, o_partd, o_partu, o_red, o_redflag, o_dp, o_pf,
-        o_pkey, o_ptmp, o_pinfo, o_skf, o_stype, o_soct, o_sz, o_smask, o_stats, o_err, total;
+        o_pkey, o_ptmp, o_pinfo, o_skf, o_stype, o_soct, o_sz, o_smask, o_stats, o_err, o_log, total;
+    int log_cap = 0;
 };
 
 int choose_points_per_tile(const lba_options &opt, int64_t total_points) {
@@ -319,6 +322,10 @@ lba_status build_plan(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, Pl
     pl.o_smask = o;   o = align256(o + nob);
     pl.o_stats = o;   o = align256(o + sizeof(double) * LBA_STATS_LEN * nw);
     pl.o_err = o;     o = align256(o + sizeof(int32_t) * 16);
+    if (opt.trial_log < 0 || opt.trial_log > 4096)
+        return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "trial_log must be in [0, 4096]");
+    pl.log_cap = opt.trial_log;
+    pl.o_log = o;     o = align256(o + sizeof(TrialRec) * (size_t)pl.log_cap * nw);
     pl.total = o;
     return LBA_OK;
 }
@@ -682,6 +689,8 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
     da.T = d_T;
     da.dp = d_dp;
     da.partu = d_partu;
+    da.log = pl.log_cap > 0 ? static_cast<TrialRec *>(W_(pl.o_log)) : nullptr;
+    da.log_cap = pl.log_cap;
     da.split = pl.upd_split;
     da.c = c;
 
@@ -767,6 +776,9 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
     m.count = 1;
     HIPCHK(timed(ctx, LBA_KCLASS_FLAGS, s, [&] { return launch_flags(m, nw, pl.max_obs, s); }));
     HIPCHK(timed(ctx, LBA_KCLASS_FINALIZE, s, [&] { return launch_finalize(m, nw, s); }));
+    if (R->log && pl.log_cap > 0)
+        HIPCHK(hipMemcpyAsync(R->log, W_(pl.o_log), sizeof(TrialRec) * (size_t)pl.log_cap * nw,
+                              hipMemcpyDeviceToHost, s));
     if (R->stats) {
         HIPCHK(hipMemcpyAsync(down, d_stats, sizeof(double) * LBA_STATS_LEN * nw, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -1181,7 +1193,8 @@ lba_status lba_tune(lba_ctx *ctx, const lba_problem *problem, const lba_batch *b
     ctx->opt.iters_round2 = 0;
     ctx->opt.points_per_tile = 0;
     ctx->prof = false;
-    lba_result R = {static_cast<double *>(T), static_cast<double *>(X), static_cast<uint8_t *>(fl), nullptr};
+    lba_result R = {static_cast<double *>(T), static_cast<double *>(X), static_cast<uint8_t *>(fl), nullptr,
+                    nullptr};
     int cfg[3];
     double best = 0.0;
     // time of one short solve (three LM steps on every window) with the tile table cfg:

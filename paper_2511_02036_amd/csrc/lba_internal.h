@@ -45,6 +45,12 @@ struct Ctl {
     int32_t term_r1, term_r2, n_outliers, round;
 };
 
+// one LM trial as k_decide records it (layout of lba_trial_record)
+struct TrialRec {
+    int32_t round, iter, trial, accepted, solve_ok, pad;
+    double lambda, F, F_trial, gain;
+};
+
 struct CamParams {
     double fx, fy, cx, cy, bf;
 };
@@ -165,6 +171,8 @@ struct DecideArgs {
     double *T;
     const double *dp;
     const double *partu;         // 4 doubles per part of a tile (split parts per tile)
+    TrialRec *log;               // per window log_cap records of its trials, or nullptr
+    int log_cap;
     int split;
     int round;                   // 1 or 2
     SolveConsts c;

@@ -40,7 +40,7 @@ class Options(C.Structure):
                 ("max_trials", C.c_int32), ("round2_robust", C.c_int32), ("check_inputs", C.c_int32),
                 ("huber2_mono", C.c_double), ("huber2_stereo", C.c_double),
                 ("chi2_mono", C.c_double), ("chi2_stereo", C.c_double), ("tau", C.c_double),
-                ("points_per_tile", C.c_int32), ("use_graphs", C.c_int32)]
+                ("points_per_tile", C.c_int32), ("use_graphs", C.c_int32), ("trial_log", C.c_int32)]
 
 
 class Intrinsics(C.Structure):
@@ -62,9 +62,15 @@ class Batch(C.Structure):
                 ("pt_off", C.c_void_p), ("obs_off", C.c_void_p)]
 
 
+class TrialRecord(C.Structure):
+    _fields_ = [("round", C.c_int32), ("iter", C.c_int32), ("trial", C.c_int32),
+                ("accepted", C.c_int32), ("solve_ok", C.c_int32), ("reserved", C.c_int32),
+                ("lam", C.c_double), ("F", C.c_double), ("F_trial", C.c_double), ("gain", C.c_double)]
+
+
 class Result(C.Structure):
     _fields_ = [("T_out", C.c_void_p), ("X_out", C.c_void_p), ("outlier", C.c_void_p),
-                ("stats", C.c_void_p)]
+                ("stats", C.c_void_p), ("log", C.c_void_p)]
 
 
 _lib = None
@@ -255,8 +261,10 @@ class Solver:
         self.X_out = torch.empty_like(prob.X)
         self.outlier = torch.empty(prob.obs_kf.shape[0], dtype=torch.uint8, device=prob.device)
         self.stats = np.zeros((prob.n_windows, STATS_LEN), dtype=np.float64)
+        self.log_cap = int(ctx.options.trial_log)
+        self.log = (TrialRecord * max(1, self.log_cap * prob.n_windows))()
         self.result = Result(self.T_out.data_ptr(), self.X_out.data_ptr(), self.outlier.data_ptr(),
-                             self.stats.ctypes.data)
+                             self.stats.ctypes.data, C.addressof(self.log) if self.log_cap > 0 else None)
 
     def run(self, stream=None):
         torch = self.prob.torch
@@ -272,6 +280,17 @@ class Solver:
     def stats_dicts(self):
         return [dict(zip(STAT_NAMES, row.tolist())) for row in self.stats]
 
+    def trial_logs(self):
+        """Per window, the list of its recorded trials (as dicts), oldest first."""
+        out = []
+        for w in range(self.prob.n_windows):
+            n = min(int(self.stats[w, 4]), self.log_cap)
+            recs = self.log[w * self.log_cap: w * self.log_cap + n]
+            out.append([dict(round=r.round, iter=r.iter, trial=r.trial, accepted=bool(r.accepted),
+                             solve_ok=bool(r.solve_ok), lam=r.lam, F=r.F, F_trial=r.F_trial, gain=r.gain)
+                        for r in recs])
+        return out
+
 
 def solve(data: dict, device="cuda", z_f32: bool = False, **options) -> dict:
     """One-shot solve of a window (or a concatenated batch).  Returns host numpy copies of
@@ -282,7 +301,7 @@ def solve(data: dict, device="cuda", z_f32: bool = False, **options) -> dict:
     prob = DeviceProblem(data, device=dev, z_f32=z_f32)
     s = Solver(ctx, prob).run()
     out = dict(T=s.T_out.cpu().numpy(), X=s.X_out.cpu().numpy(),
-               outlier=s.outlier.cpu().numpy().astype(bool), stats=s.stats_dicts())
+               outlier=s.outlier.cpu().numpy().astype(bool), stats=s.stats_dicts(), log=s.trial_logs())
     ctx.close()
     return out
 

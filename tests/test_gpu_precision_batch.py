@@ -94,17 +94,57 @@ def c5():
     return ws, synth.concat(ws)
 
 
-def test_c5_full_batch_mixed_sampled_windows(c5):
+def _oracle_all(ws, threads=16):
+    """The FP64 oracle on every window, one window per thread (ctypes releases the GIL)."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        return list(ex.map(lbaref.solve, ws))
+
+
+def test_c5_full_batch_mixed_every_window(c5):
+    """All 256 windows of the batch, solved together in the mixed form on FP32
+    measurements, against the oracle on the same FP32-rounded measurements: final cost
+    within 1e-4 relative and RMS reprojection difference within 0.01 px in every window.
+    Outlier flags may differ where an observation's s lies within the FP32 path's error of
+    its threshold; their count is recorded with the other per-result errors."""
     ws, cat = c5
-    print(f"case c5 windows={len(ws)} N={len(cat['obs_kf'])}", flush=True)
+    print(f"case c5 mixed windows={len(ws)} N={len(cat['obs_kf'])}", flush=True)
     g = lba.solve(cat, device="cuda:0", precision="mixed", z_f32=True)
     st = g["stats"]
     assert all(s["iters_r1"] >= 1 and s["iters_r2"] >= 1 for s in st)
-    Ns = np.diff(cat["obs_off"])
-    sample = sorted({int(np.argmin(Ns)), int(np.argsort(Ns)[len(Ns) // 2]), int(np.argmax(Ns))})
-    for i in sample:
+    wrs = [round_z_f32(w) for w in ws]
+    refs = _oracle_all(wrs)
+    rows = []
+    for i, (wr, r) in enumerate(zip(wrs, refs)):
         ks, ps, os_ = window_slice(cat, i)
-        wr = round_z_f32(ws[i])
-        r = lbaref.solve(wr)
-        m = assert_mixed_tolerances(wr, g["T"][ks], g["X"][ps], st[i], r)
-        _record(f"c5_mixed_window{i}_N{int(Ns[i])}", m)
+        m = mixed_metrics(wr, g["T"][ks], g["X"][ps], st[i], r)
+        m["flags_differ"] = int((g["outlier"][os_] != r["outlier"]).sum())
+        m["window"] = i
+        m["N"] = len(wr["obs_kf"])
+        rows.append(m)
+    worst = max(rows, key=lambda m: m["cost_rel"])
+    worst_px = max(rows, key=lambda m: m["rms_px"])
+    _record("c5_mixed_all_windows", dict(
+        windows=len(rows), cost_rel_max=worst["cost_rel"], cost_rel_worst_window=worst,
+        rms_px_max=worst_px["rms_px"], pos_m_max=max(m["pos_m"] for m in rows),
+        rot_rad_max=max(m["rot_rad"] for m in rows), flags_differ_total=sum(m["flags_differ"] for m in rows),
+        cost_rel_median=float(np.median([m["cost_rel"] for m in rows]))))
+    for m in rows:
+        assert m["cost_rel"] <= 1e-4, m
+        assert m["rms_px"] <= 0.01, m
+
+
+def test_c5_full_batch_fp64_every_window(c5):
+    """The same 256 windows solved together in plain FP64 match the oracle window by
+    window at the FP64 bar (1e-9 cost, 1e-8 states, flags outside the band)."""
+    ws, cat = c5
+    print(f"case c5 fp64 windows={len(ws)} N={len(cat['obs_kf'])}", flush=True)
+    g = lba.solve(cat, device="cuda:0")
+    refs = _oracle_all(ws)
+    worst = 0.0
+    for i, (w, r) in enumerate(zip(ws, refs)):
+        ks, ps, os_ = window_slice(cat, i)
+        assert_fp64_parity(w, g["T"][ks], g["X"][ps], g["outlier"][os_], g["stats"][i], r)
+        Fr = r["stats"]["F_final"]
+        worst = max(worst, abs(g["stats"][i]["F_final"] - Fr) / Fr)
+    _record("c5_fp64_all_windows", dict(windows=len(ws), cost_rel_max=worst))
