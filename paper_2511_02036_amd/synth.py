@@ -356,3 +356,173 @@ def concat(windows: list[dict]) -> dict:
         "kf_off": kf_off, "pt_off": pt_off, "obs_off": ob_off,
     }
     return cat
+
+
+# ----------------------------------------------------------------------------------------
+# keyframe store for the correspondence and fusion searches
+# ----------------------------------------------------------------------------------------
+DESC_WORDS = 8   # 256-bit binary descriptors, eight 32-bit words
+
+
+def _random_descriptors(rng: np.random.Generator, n: int) -> np.ndarray:
+    return rng.integers(0, 1 << 32, size=(n, DESC_WORDS), dtype=np.uint64).astype(np.uint32)
+
+
+def _flip_bits(rng: np.random.Generator, d: np.ndarray, p: float) -> np.ndarray:
+    """Each of the 256 bits of each descriptor flipped independently with probability p."""
+    bits = rng.uniform(size=(d.shape[0], DESC_WORDS, 32)) < p
+    mask = (bits.astype(np.uint64) << np.arange(32, dtype=np.uint64)).sum(axis=2).astype(np.uint32)
+    return d ^ mask
+
+
+def keyframe_store(seed: int = 5, K: int = 80, M: int = 30000, kp_per_kf: int = 1200,
+                   walk_length: float = 16.0, true_frac: float = 0.8, free_p: float = 0.6,
+                   flip_p: float = 0.05, stereo_p: float = 0.7) -> dict:
+    """Keyframes of a local map with their keypoints, as a GPU-resident keyframe store
+    would hold them: poses, keypoint positions (left u, v and right uR or -1), octaves,
+    256-bit descriptors and a 'free' flag (the keypoint has no map point yet).
+
+    Each keyframe gets kp_per_kf keypoints: true_frac of them are projections of visible
+    map points (octave U{0..7}, pixel noise N(0, 1.2^octave), the point's descriptor with
+    each bit flipped with probability flip_p, a right coordinate with probability
+    stereo_p when the point is stereo-visible), the rest distractors at uniform image
+    positions with uniform random descriptors.  Keypoints are shuffled within their
+    keyframe.  Draw order: trajectory, points, point descriptors, then per keyframe:
+    selection, octaves, noise, stereo choice, flips, distractors, shuffle, free flags."""
+    rng = np.random.default_rng(seed)
+    T, centers = _walk_trajectory(rng, K, walk_length)
+    anchor = rng.integers(0, K, size=M)
+    uu = rng.uniform(0.0, WIDTH, size=M)
+    vv = rng.uniform(0.0, HEIGHT, size=M)
+    dd = rng.uniform(1.0, 12.0, size=M)
+    P_c = np.stack([(uu - CX) / FX * dd, (vv - CY) / FY * dd, dd], axis=1)
+    R_wc = np.transpose(T[anchor, :, :3], (0, 2, 1))
+    X = np.einsum("nij,nj->ni", R_wc, P_c) + centers[anchor]
+    pdesc = _random_descriptors(rng, M)
+    z, u, v, ur = _project(T, X)
+    vis = _visible(z, u, v)
+    n_true = int(round(true_frac * kp_per_kf))
+    cols = dict(u=[], v=[], ur=[], oct=[], free=[], desc=[], pt=[])
+    kp_off = [0]
+    for k in range(K):
+        cand = np.nonzero(vis[:, k])[0]
+        sel = np.sort(rng.choice(cand, size=min(n_true, len(cand)), replace=False))
+        nt = len(sel)
+        octv = rng.integers(0, N_LEVELS, size=nt)
+        sig = SCALE_FACTOR ** octv
+        nz = rng.normal(size=(3, nt)) * sig[None, :]
+        st = (rng.uniform(size=nt) < stereo_p) & (ur[sel, k] >= 0.0)
+        ku = u[sel, k] + nz[0]
+        kv = v[sel, k] + nz[1]
+        kur = np.where(st, ur[sel, k] + nz[2], -1.0)
+        kd = _flip_bits(rng, pdesc[sel], flip_p)
+        nd = kp_per_kf - nt
+        du = rng.uniform(0.0, WIDTH, size=nd)
+        dv = rng.uniform(0.0, HEIGHT, size=nd)
+        doct = rng.integers(0, N_LEVELS, size=nd)
+        dst = rng.uniform(size=nd) < stereo_p
+        dur = np.where(dst, du - rng.uniform(0.0, BF / 1.0, size=nd), -1.0)
+        ddesc = _random_descriptors(rng, nd)
+        perm = rng.permutation(kp_per_kf)
+        cols["u"].append(np.concatenate([ku, du])[perm])
+        cols["v"].append(np.concatenate([kv, dv])[perm])
+        cols["ur"].append(np.concatenate([kur, dur])[perm])
+        cols["oct"].append(np.concatenate([octv, doct])[perm])
+        cols["desc"].append(np.concatenate([kd, ddesc])[perm])
+        cols["pt"].append(np.concatenate([sel, np.full(nd, -1)])[perm])
+        cols["free"].append(rng.uniform(size=kp_per_kf) < free_p)
+        kp_off.append(kp_off[-1] + kp_per_kf)
+    return {
+        "T_cw": T.reshape(K, 12).copy(),
+        "centers": centers,
+        "kp_off": np.array(kp_off, dtype=np.int32),
+        "kp_u": np.concatenate(cols["u"]).astype(np.float32),
+        "kp_v": np.concatenate(cols["v"]).astype(np.float32),
+        "kp_ur": np.concatenate(cols["ur"]).astype(np.float32),
+        "kp_oct": np.concatenate(cols["oct"]).astype(np.uint8),
+        "kp_free": np.concatenate(cols["free"]).astype(np.uint8),
+        "kp_desc": np.ascontiguousarray(np.concatenate(cols["desc"]), dtype=np.uint32),
+        "kp_pt": np.concatenate(cols["pt"]).astype(np.int32),
+        "X_true": X,
+        "pt_desc": pdesc,
+        "sigma2": SIGMA2.copy(),
+        "scale": np.array([SCALE_FACTOR ** o for o in range(N_LEVELS)]),
+        "cam": CAM.copy(),
+        "width": WIDTH,
+        "height": HEIGHT,
+    }
+
+
+def nearest_keyframes(store: dict, k: int, n: int) -> np.ndarray:
+    """The n keyframes other than k with the closest camera centres (stable order)."""
+    c = store["centers"]
+    d = np.linalg.norm(c - c[k], axis=1)
+    d[k] = np.inf
+    return np.argsort(d, kind="stable")[:n].astype(np.int32)
+
+
+def correspondence_queries(store: dict, n_cur: int = 64, n_nbr: int = 10):
+    """(current, neighbour) keyframe pairs: each of the last n_cur keyframes with its
+    n_nbr nearest keyframes."""
+    K = len(store["kp_off"]) - 1
+    cur, nbr = [], []
+    for k in range(K - n_cur, K):
+        for m in nearest_keyframes(store, k, n_nbr):
+            cur.append(k)
+            nbr.append(int(m))
+    return np.array(cur, dtype=np.int32), np.array(nbr, dtype=np.int32)
+
+
+def fusion_points(store: dict, seed: int = 6, n_cur: int = 64, n_nbr: int = 20, pos_sigma: float = 0.02,
+                  flip_p: float = 0.02):
+    """Map points of the last n_cur keyframes (the true points behind each keyframe's
+    associated, i.e. non-free, keypoints), with what a map point carries for the fusion
+    search: position (truth + N(0, pos_sigma) per axis), descriptor (the point's with
+    bits flipped with probability flip_p), mean viewing direction over the store's
+    keyframes that see it, and the distance range of scale invariance (the distance from
+    the keyframe times 1.2^octave of its keypoint, down to that over 1.2^7).  Returns the
+    points concatenated over keyframes and the queries (point range, neighbour keyframe):
+    every keyframe's points against its n_nbr nearest keyframes."""
+    rng = np.random.default_rng(seed)
+    K = len(store["kp_off"]) - 1
+    cen = store["centers"]
+    kp_pt, kp_off = store["kp_pt"], store["kp_off"]
+    seen_by = {}
+    for k in range(K):
+        for p in kp_pt[kp_off[k]:kp_off[k + 1]]:
+            if p >= 0:
+                seen_by.setdefault(int(p), []).append(k)
+    X, D, Nrm, dmin, dmax = [], [], [], [], []
+    q_p0, q_p1, q_nbr = [], [], []
+    for k in range(K - n_cur, K):
+        sl = slice(kp_off[k], kp_off[k + 1])
+        pts = kp_pt[sl]
+        octs = store["kp_oct"][sl]
+        keep = (pts >= 0) & (store["kp_free"][sl] == 0)
+        p0 = sum(len(x) for x in X)
+        P = pts[keep]
+        Xt = store["X_true"][P]
+        nv = np.stack([np.mean([(Xt[i] - cen[m]) / np.linalg.norm(Xt[i] - cen[m]) for m in seen_by[int(p)]],
+                               axis=0) for i, p in enumerate(P)]) if len(P) else np.zeros((0, 3))
+        nv = nv / np.linalg.norm(nv, axis=1, keepdims=True) if len(P) else nv
+        dist = np.linalg.norm(Xt - cen[k], axis=1)
+        mx = dist * SCALE_FACTOR ** octs[keep].astype(np.float64)
+        X.append(Xt + rng.normal(0.0, pos_sigma, size=Xt.shape))
+        D.append(_flip_bits(rng, store["pt_desc"][P], flip_p))
+        Nrm.append(nv)
+        dmax.append(mx)
+        dmin.append(mx / SCALE_FACTOR ** (N_LEVELS - 1))
+        p1 = p0 + len(P)
+        for m in nearest_keyframes(store, k, n_nbr):
+            q_p0.append(p0)
+            q_p1.append(p1)
+            q_nbr.append(int(m))
+    pts = {
+        "X": np.concatenate(X),
+        "desc": np.ascontiguousarray(np.concatenate(D), dtype=np.uint32),
+        "normal": np.concatenate(Nrm),
+        "dmin": np.concatenate(dmin),
+        "dmax": np.concatenate(dmax),
+    }
+    q = (np.array(q_p0, dtype=np.int32), np.array(q_p1, dtype=np.int32), np.array(q_nbr, dtype=np.int32))
+    return pts, q
