@@ -63,6 +63,20 @@ WORKLOADS = {
              "per point, even windows monocular, odd 70/30 stereo/mono; one step = FP32 robust-cost "
              "forward + hand-written backward (gradients for poses, points, measurements) of all windows",
         precision="fp64", z_f32=True, compare_plain=False),
+    "corr_search": dict(
+        desc="keypoint correspondence search (map-point creation), seed 5: GPU-resident keyframe store of "
+             "80 keyframes x 1,200 keypoints (256-bit descriptors, octaves U{0..7}, 70% stereo, 60% without "
+             "a map point), the last 64 keyframes each against its 10 nearest: 640 keyframe pairs per step",
+        precision="i8+f64", z_f32=False, compare_plain=False),
+    "fusion_search": dict(
+        desc="map-point fusion candidate search, seeds 5 and 6: the same store; the map points of the last 64 "
+             "keyframes (about 390 each) against each keyframe's 20 nearest: 1,280 queries, about 496k "
+             "point-keyframe pairs per step",
+        precision="f64", z_f32=False, compare_plain=False),
+    "culling_batched": dict(
+        desc="keyframe-culling counters over the observations of the 256-window batch (seed 4; 18M "
+             "observations, 2.6M points, 5,700 keyframes, global indices, every 13th observation inactive)",
+        precision="i32", z_f32=False, compare_plain=False),
     "c3_precision_mixed": dict(
         desc="precision form, seed 2: 30 optimisable + 20 fixed stereo keyframes, 20,000 points, "
              "10 observations per point, FP32 bulk + FP64 reduced solve, 5+10 LM iterations",
@@ -358,6 +372,148 @@ def bench_cost_layer(args, spec):
     print(json.dumps(out), flush=True)
 
 
+# dense int8 matrix-core peak of MI355X (published; no sparsity)
+INT8_PEAK_TOPS = 5000.0
+
+
+def map_search_job(name):
+    """(job, per-launch work record, oracle sample runner) of a local-mapping workload."""
+    import numpy as np
+    from paper_2511_02036_amd import lmap, synth
+    if name == "culling_batched":
+        wins = synth.c5_windows(seed=4)
+        kf, pt, oc = [], [], []
+        k0 = p0 = 0
+        for w in wins:
+            kf.append(w["obs_kf"] + k0)
+            pt.append(w["obs_pt"] + p0)
+            oc.append(w["obs_oct"])
+            k0 += len(w["fixed"])
+            p0 += len(w["X"])
+        kf, pt, oc = np.concatenate(kf), np.concatenate(pt), np.concatenate(oc)
+        active = np.ones(len(kf), np.uint8)
+        active[::13] = 0
+        job = lmap.Culling(k0, p0, kf, pt, oc, active=active)
+        n_obs, n_pt = len(kf), p0
+        work = dict(kind="culling", n_obs=n_obs, n_pt=n_pt, n_kf=k0,
+                    # count: point, octave, flag (6 B) per observation + one 4-byte counter add;
+                    # redundancy: keyframe, point, octave, flag (10 B) + the point's 8 counters
+                    bytes={"cull_count": n_obs * 10 + n_pt * 8 * 4,
+                           "cull_redundant": n_obs * 10 + n_pt * 8 * 4 + k0 * 8})
+
+        def oracle_sample(budget_s):
+            from oracle import mapref
+            order = np.argsort([len(w["obs_kf"]) for w in wins])
+            t0 = time.perf_counter()
+            n = obs = 0
+            while n < len(order) and time.perf_counter() - t0 < budget_s:
+                w = wins[order[n]]
+                mapref.culling(w)
+                obs += len(w["obs_kf"])
+                n += 1
+            el = time.perf_counter() - t0
+            return obs / el, f"the {n} smallest of the 256 windows ({obs} observations) in {el:.1f} s, one thread"
+        return job, work, oracle_sample, "observations/s", n_obs
+    st = synth.keyframe_store()
+    ds = lmap.DeviceStore(st)
+    if name == "corr_search":
+        cur, nbr = synth.correspondence_queries(st)
+        job = lmap.Correspondence(ds, cur, nbr)
+        free = ds.upload_free(st["kp_free"])
+        ko, fr = st["kp_off"], st["kp_free"].astype(np.int64)
+        nfree = np.array([fr[ko[k]:ko[k + 1]].sum() for k in range(len(ko) - 1)])
+        pairs = int((nfree[cur] * nfree[nbr]).sum())
+        work = dict(kind="corr", pairs=pairs, ops=2 * 256 * pairs, queries=len(cur))
+        run = lambda: job.run(free, check=False)
+
+        def oracle_sample(budget_s):
+            from oracle import mapref
+            t0 = time.perf_counter()
+            n = 0
+            while n < len(cur) and time.perf_counter() - t0 < budget_s:
+                mapref.correspondence(st, cur[n:n + 4], nbr[n:n + 4])
+                n += 4
+            el = time.perf_counter() - t0
+            return n / el, f"the first {n} of {len(cur)} keyframe pairs in {el:.1f} s, one thread"
+        job.run_step = run
+        return job, work, oracle_sample, "keyframe-pairs/s", len(cur)
+    pts, q = synth.fusion_points(st)
+    job = lmap.Fusion(ds, pts, q)
+    entries = int(np.sum(q[1] - q[0]))
+    # per (point, keyframe) entry: the point's position, direction, range and descriptor
+    # (24 + 24 + 16 + 32 B) and its two outputs (8 B); per query the keyframe's pose (96 B)
+    work = dict(kind="fusion", entries=entries, bytes={"fuse": entries * 104 + len(q[0]) * 96})
+
+    def oracle_sample(budget_s):
+        from oracle import mapref
+        t0 = time.perf_counter()
+        n = 0
+        while n < len(q[0]) and time.perf_counter() - t0 < budget_s:
+            sl = slice(n, n + 20)
+            mapref.fusion(st, pts, (q[0][sl], q[1][sl], q[2][sl]))
+            n += 20
+        el = time.perf_counter() - t0
+        done = int(np.sum(q[1][:n] - q[0][:n]))
+        return done / el, f"the first {n} of {len(q[0])} queries ({done} point-keyframe pairs) in {el:.1f} s, one thread"
+    return job, work, oracle_sample, "point-keyframe-pairs/s", entries
+
+
+def bench_map_search(args, spec):
+    """One step = one call of the search over the whole workload, inputs resident on the GPU."""
+    import torch
+    from paper_2511_02036_amd import lmap
+    dev = torch.device("cuda:0")
+    t_gen = time.perf_counter()
+    job, work, oracle_sample, unit, units_per_step = map_search_job(args.workload)
+    step = getattr(job, "run_step", None) or (lambda: job.run(check=False))
+    print(f"bench: workload={args.workload} set up in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    steps = max(args.steps, 1) * 10
+    lmap.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    pel = time.perf_counter() - t0
+    prof = lmap.profile_read()
+    lmap.profile(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    kern = {k: dict(launches=n, mean_us=1e3 * ms / n) for k, (n, ms) in prof.items() if n}
+    if work["kind"] == "corr":
+        mu = kern["corr_search"]["mean_us"]
+        tops = work["ops"] / (mu * 1e-6) / 1e12
+        roof = dict(kernel="corr_search", bound="mfma", achieved=tops, peak=INT8_PEAK_TOPS, unit="TOP/s",
+                    frac=tops / INT8_PEAK_TOPS, traffic=None, ops_per_launch=work["ops"],
+                    keypoint_pairs_per_launch=work["pairs"], mean_us=mu,
+                    note="int8 products of the +-1 descriptor bytes: 2 x 256 operations per pair of free "
+                         "keypoints (the pairs the search must compare)")
+    else:
+        dom = max(work["bytes"], key=lambda k: kern.get(k, {"mean_us": 0})["mean_us"])
+        mu = kern[dom]["mean_us"]
+        gbs = work["bytes"][dom] / (mu * 1e-6) / 1e9
+        roof = dict(kernel=dom, bound="hbm", achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s", frac=gbs / HBM_PEAK_GBS,
+                    traffic=None, bytes_per_launch=work["bytes"][dom], mean_us=mu)
+    out = {"metric": f"{args.workload}: {unit}", "value": units_per_step * steps / el, "unit": unit, "n_gpus": 1,
+           "steps": steps, "warmup": args.warmup, "ms_per_step": 1e3 * el / steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": spec["precision"], "data": "synthetic",
+           "config": {"workload": args.workload, "description": spec["desc"],
+                      **{k: v for k, v in work.items() if k not in ("bytes", "kind")}},
+           "roofline": roof, "kernels_us_mean": {k: round(v["mean_us"], 2) for k, v in kern.items()},
+           "profiled": {"ms_per_step": 1e3 * pel / steps,
+                        "note": "the same steps with per-kernel HIP events (each call then waits for its kernels)"}}
+    if not args.no_cpu_baseline:
+        v, sample = oracle_sample(10.0)
+        out["cpu_baseline"] = dict(value=v, unit=unit, cores=1, kind="oracle", sample=sample, **host_description())
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -392,6 +548,9 @@ def main():
         del src, dst
     if args.workload.startswith("c4"):
         bench_cost_layer(args, spec)
+        return
+    if args.workload in ("corr_search", "fusion_search", "culling_batched"):
+        bench_map_search(args, spec)
         return
     t_gen = time.perf_counter()
     windows = make_windows(args.workload)
