@@ -173,6 +173,23 @@ lmap_status lmap_correspondence(const lmap_store *store, const lmap_corr_params 
                                 int32_t *match, int32_t *dist, void *workspace,
                                 size_t workspace_bytes, int32_t check, void *stream);
 
+/* ---- correspondence search without allocation ---------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): lmap_correspondence with its workspace
+ * in a static device array of LMAP_NOALLOC_SCRATCH_BYTES on each GPU, which the library
+ * holds until the process ends; nothing is allocated or freed.  A problem whose
+ * lmap_corr_workspace_size exceeds that size returns LMAP_ERR_WORKSPACE_TOO_SMALL.  Every
+ * call on a GPU shares that GPU's array, and each call sets what must start cleared:
+ * calls that overlap on one GPU (other streams or threads) race and must be ordered by
+ * the caller.  The array's device address is looked up on the first call on each device,
+ * which must then be the current device.  With check set the call synchronises the
+ * stream once (under graph capture, pass 0). */
+#define LMAP_NOALLOC_SCRATCH_BYTES (16u << 20)
+lmap_status lmap_correspondence_noalloc(const lmap_store *store, const lmap_corr_params *params,
+                                        const uint8_t *kp_free, int32_t n_q, const int32_t *cur,
+                                        const int32_t *nbr, const int64_t *out_off, int64_t n_out,
+                                        int32_t *match, int32_t *dist, int32_t check, void *stream);
+
 /* ---- fusion candidate search (Sections III-B, IV-D) --------------------------------------
  * n_q queries: map points [p0[q], p1[q]) against keyframe nbr[q] (DEVICE arrays).  One
  * output entry per (query, point), from out_off[q] on (DEVICE n_q + 1, running sum of

@@ -304,11 +304,19 @@ lmap_status lmap_corr_workspace_size(const lmap_store *store, int32_t n_q, size_
     return LMAP_OK;
 }
 
-lmap_status lmap_correspondence(const lmap_store *store, const lmap_corr_params *params, const uint8_t *kp_free,
-                                int32_t n_q, const int32_t *cur, const int32_t *nbr, const int64_t *out_off,
-                                int64_t n_out, int32_t *match, int32_t *dist, void *workspace,
-                                size_t workspace_bytes, int32_t check, void *stream) {
-    g_err.clear();
+}  // extern "C"
+
+// The no-allocation variant's scratch: one copy per GPU, in the code object's device
+// memory, for the life of the process.  Host code must not pass `scratch` itself to a
+// kernel (on the host it is only a stand-in symbol); its device address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[LMAP_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+lmap_status corr_impl(const lmap_store *store, const lmap_corr_params *params, const uint8_t *kp_free, int32_t n_q,
+                      const int32_t *cur, const int32_t *nbr, const int64_t *out_off, int64_t n_out, int32_t *match,
+                      int32_t *dist, void *workspace, size_t workspace_bytes, int32_t check, void *stream) {
     CorrArgs a;
     memset(&a, 0, sizeof(a));
     lmap_status st = store_view(store, true, &a.s);
@@ -360,6 +368,59 @@ lmap_status lmap_correspondence(const lmap_store *store, const lmap_corr_params 
     launch_corr(a, s);
     HIPCHK(hipGetLastError());
     return prof_collect(s);
+}
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+lmap_status scratch_address(void **out) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(LMAP_ERR_UNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p || !aligned256(p)) return fail(LMAP_ERR_HIP, "scratch symbol address not usable");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return LMAP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lmap_status lmap_correspondence(const lmap_store *store, const lmap_corr_params *params, const uint8_t *kp_free,
+                                int32_t n_q, const int32_t *cur, const int32_t *nbr, const int64_t *out_off,
+                                int64_t n_out, int32_t *match, int32_t *dist, void *workspace,
+                                size_t workspace_bytes, int32_t check, void *stream) {
+    g_err.clear();
+    return corr_impl(store, params, kp_free, n_q, cur, nbr, out_off, n_out, match, dist, workspace, workspace_bytes,
+                     check, stream);
+}
+
+lmap_status lmap_correspondence_noalloc(const lmap_store *store, const lmap_corr_params *params,
+                                        const uint8_t *kp_free, int32_t n_q, const int32_t *cur, const int32_t *nbr,
+                                        const int64_t *out_off, int64_t n_out, int32_t *match, int32_t *dist,
+                                        int32_t check, void *stream) {
+    g_err.clear();
+    StoreView v;
+    lmap_status st = store_view(store, true, &v);
+    if (st != LMAP_OK) return st;
+    if (n_q < 0) return fail(LMAP_ERR_INVALID_ARGUMENT, "n_q must be >= 0");
+    const size_t need = corr_layout(*store, n_q).total;
+    if (need > LMAP_NOALLOC_SCRATCH_BYTES)
+        return fail(LMAP_ERR_WORKSPACE_TOO_SMALL,
+                    "this problem needs %zu bytes of scratch, above the %u the no-allocation entry point holds", need,
+                    (unsigned)LMAP_NOALLOC_SCRATCH_BYTES);
+    void *ws = nullptr;
+    st = scratch_address(&ws);
+    if (st != LMAP_OK) return st;
+    return corr_impl(store, params, kp_free, n_q, cur, nbr, out_off, n_out, match, dist, ws,
+                     LMAP_NOALLOC_SCRATCH_BYTES, check, stream);
 }
 
 lmap_status lmap_fuse_workspace_size(size_t *bytes) {

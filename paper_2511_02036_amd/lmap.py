@@ -21,7 +21,10 @@ STATUS = {0: "ok", -1: "invalid argument", -3: "HIP runtime error", -4: "workspa
 EXPORTS = ["lmap_abi_version", "lmap_status_string", "lmap_last_error", "lmap_default_corr_params",
            "lmap_default_fuse_params", "lmap_default_cull_params", "lmap_index_size", "lmap_index_build",
            "lmap_corr_workspace_size", "lmap_correspondence", "lmap_fuse_workspace_size", "lmap_fusion",
-           "lmap_cull_workspace_size", "lmap_culling", "lmap_profile_enable", "lmap_profile_read"]
+           "lmap_cull_workspace_size", "lmap_culling", "lmap_profile_enable", "lmap_profile_read",
+           "lmap_correspondence_noalloc"]
+
+NOALLOC_SCRATCH_BYTES = 16 << 20
 
 KERNEL_CLASSES = ["index", "prep", "corr_search", "corr_resolve", "fuse", "cull_count", "cull_redundant",
                   "cull_decide", "check"]
@@ -81,6 +84,8 @@ def library():
         L.lmap_cull_workspace_size.argtypes = [C.POINTER(sz)]
         L.lmap_culling.argtypes = [i32, i32, i32, i32, vp, vp, vp, vp, vp, C.POINTER(CullParams), vp, vp, vp, vp,
                                    vp, sz, i32, vp]
+        L.lmap_correspondence_noalloc.argtypes = [C.POINTER(Store), C.POINTER(CorrParams), vp, i32, vp, vp, vp,
+                                                  i64, vp, vp, i32, vp]
         L.lmap_profile_enable.argtypes = [i32]
         L.lmap_profile_read.argtypes = [i32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
         for name in EXPORTS[6:]:
@@ -226,6 +231,15 @@ class Correspondence:
                                              _ptr(self.cur), _ptr(self.nbr), _ptr(self.off), self.n_out,
                                              _ptr(self.match), _ptr(self.dist), _ptr(self.ws), self.ws.numel(),
                                              int(check), st), "lmap_correspondence")
+
+    def run_noalloc(self, kp_free_dev, params: CorrParams | None = None, check: bool = True, stream=None):
+        """The same search through lmap_correspondence_noalloc (library-held scratch)."""
+        p = params or corr_params()
+        st = C.c_void_p(stream.cuda_stream) if stream is not None else _stream(self.ds.device)
+        _check(library().lmap_correspondence_noalloc(C.byref(self.ds.S), C.byref(p), _ptr(kp_free_dev), self.n_q,
+                                                     _ptr(self.cur), _ptr(self.nbr), _ptr(self.off), self.n_out,
+                                                     _ptr(self.match), _ptr(self.dist), int(check), st),
+               "lmap_correspondence_noalloc")
 
     def result(self):
         return (self.match[:self.n_out].cpu().numpy(), self.dist[:self.n_out].cpu().numpy(), self.off_np)
