@@ -44,6 +44,10 @@
 #include <stdlib.h>
 #include <string.h>
 
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
 /* ------------------------------------------------------------------------------------ */
 /* public structs (mirrored by the ctypes wrapper in lbaref.py)                           */
 /* ------------------------------------------------------------------------------------ */
@@ -454,19 +458,10 @@ static int reduced_system(const ref_problem *P, const blocks_t *B, const uint8_t
     return 0;
 }
 
-/* Full damped step: Schur-reduced pose solve by dense Cholesky, then back-substitution.
- * Returns 0 on success, 1 if a point block or S is not positive definite. */
-static int schur_step(const ref_problem *P, const blocks_t *B, const uint8_t *active, double lambda,
-                      double *dp, double *dl) {
-    int n = 6 * B->Kopt;
-    double *S = (double *)malloc(sizeof(double) * ((size_t)n * n + 1));
-    int fail = reduced_system(P, B, active, lambda, S, dp);
-    if (!fail && n > 0) {
-        fail = lbaref_cholesky(n, S);
-        if (!fail) chol_solve(n, S, dp);
-    }
-    free(S);
-    if (fail) return 1;
+/* Point back-substitution for a pose step: dl_j = V_j^-1 (bl_j - sum_a W_a^T dp_k(a)).
+ * Returns 0, or 1 if a point block is not positive definite. */
+static int back_substitute(const ref_problem *P, const blocks_t *B, const uint8_t *active, double lambda,
+                           const double *dp, double *dl) {
     for (int j = 0; j < B->M; ++j) {
         double V[9], Vi[9], rhs[3];
         for (int q = 0; q < 9; ++q) V[q] = B->Hll[j * 9 + q] + ((q % 4 == 0) ? lambda : 0.0);
@@ -481,6 +476,22 @@ static int schur_step(const ref_problem *P, const blocks_t *B, const uint8_t *ac
         matmul(Vi, rhs, dl + 3 * j, 3, 3, 1);
     }
     return 0;
+}
+
+/* Full damped step: Schur-reduced pose solve by dense Cholesky, then back-substitution.
+ * Returns 0 on success, 1 if a point block or S is not positive definite. */
+static int schur_step(const ref_problem *P, const blocks_t *B, const uint8_t *active, double lambda,
+                      double *dp, double *dl) {
+    int n = 6 * B->Kopt;
+    double *S = (double *)malloc(sizeof(double) * ((size_t)n * n + 1));
+    int fail = reduced_system(P, B, active, lambda, S, dp);
+    if (!fail && n > 0) {
+        fail = lbaref_cholesky(n, S);
+        if (!fail) chol_solve(n, S, dp);
+    }
+    free(S);
+    if (fail) return 1;
+    return back_substitute(P, B, active, lambda, dp, dl);
 }
 
 static void retract(const blocks_t *B, const double *T, const double *X, const double *dp,
@@ -779,4 +790,572 @@ double lbaref_cost_grad(const ref_problem *P, const ref_options *O, const double
     free(T);
     free(gl);
     return F;
+}
+
+/* ==================================================================================== */
+/* Stereo-inertial local bundle adjustment                                              */
+/*                                                                                      */
+/* The paper's local bundle adjustment minimises reprojection errors, and in visual-    */
+/* inertial systems inertial residuals as well (Section III-C); its experiments run     */
+/* stereo-inertial (Section V-A).  It gives no equations for the inertial terms; the     */
+/* reading here is the preintegrated-IMU factor of Forster, Carlone, Dellaert and         */
+/* Scaramuzza, "On-Manifold Preintegration for Real-Time Visual-Inertial Odometry"       */
+/* (IEEE T-RO 2017), Section VI, with a bias random-walk factor:                          */
+/*                                                                                      */
+/*   states     per keyframe the camera pose T_cw (as above), the body velocity v in    */
+/*              the world frame, gyroscope bias bg and accelerometer bias ba; fixed      */
+/*              keyframes hold all of them;                                               */
+/*   body pose  R = R_cw^T R_cb, p = R_cw^T (t_cb - t_cw) for the body-to-camera         */
+/*              transform T_cb = [R_cb | t_cb];                                           */
+/*   residual   for a measurement (dR, dv, dp, dt, biases bg_bar / ba_bar it was          */
+/*              integrated with, bias Jacobians J_Rg, J_vg, J_va, J_pg, J_pa) between    */
+/*              keyframes i and j, with dbg = bg_i - bg_bar, dba = ba_i - ba_bar:          */
+/*                r_R = Log((dR Exp(J_Rg dbg))^T R_i^T R_j)                              */
+/*                r_v = R_i^T (v_j - v_i - g dt) - (dv + J_vg dbg + J_va dba)             */
+/*                r_p = R_i^T (p_j - p_i - v_i dt - g dt^2 / 2) - (dp + J_pg dbg + J_pa dba)*/
+/*                r_bg = bg_j - bg_i,  r_ba = ba_j - ba_i                                 */
+/*   cost       r9^T Info r9 + info_bg |r_bg|^2 + info_ba |r_ba|^2 per measurement       */
+/*              (r9 = (r_R, r_v, r_p); no robust kernel, no factor 1/2, like the          */
+/*              reprojection terms), added to the reprojection cost;                      */
+/*   step       the normal equations gain the inertial blocks on 15 unknowns per          */
+/*              optimisable keyframe (twist, dv, dbg, dba); the points are eliminated     */
+/*              as before, so the reduced system has 15 Kopt unknowns; lambda is added    */
+/*              to every diagonal entry; v, bg, ba move additively.                        */
+/* ==================================================================================== */
+
+typedef struct {
+    int32_t n_edges, pad;
+    const int32_t *edge_i, *edge_j;   /* keyframes of each measurement */
+    const double *dt;                 /* n_edges */
+    const double *dR;                 /* n_edges x 9 */
+    const double *dv, *dp;            /* n_edges x 3 */
+    const double *J_Rg, *J_vg, *J_va, *J_pg, *J_pa;   /* n_edges x 9 each */
+    const double *bg_bar, *ba_bar;    /* n_edges x 3 */
+    const double *info;               /* n_edges x 81, information of (r_R, r_v, r_p) */
+    const double *info_bg, *info_ba;  /* n_edges */
+    const double *T_cb;               /* 12 */
+    double g[3];                      /* gravity, world frame */
+} ref_inertial;
+
+/* SO(3) exponential R = I + A W + B W^2 (coefficients as for SE(3) above). */
+static void so3_exp(const double w[3], double R[9]) {
+    double th = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+    double A, B, C, W[9], W2[9];
+    so3_coeffs(th, &A, &B, &C);
+    hat(w, W);
+    matmul(W, W, W2, 3, 3, 3);
+    for (int i = 0; i < 9; ++i) R[i] = ((i % 4 == 0) ? 1.0 : 0.0) + A * W[i] + B * W2[i];
+}
+
+/* SO(3) logarithm: the angle from atan2(|sin|, cos), so that small angles keep their
+ * digits; near pi the axis comes from the symmetric part R + I. */
+void lbaref_so3_log(const double R[9], double w[3]) {
+    double vx = 0.5 * (R[7] - R[5]), vy = 0.5 * (R[2] - R[6]), vz = 0.5 * (R[3] - R[1]);
+    double s = sqrt(vx * vx + vy * vy + vz * vz);
+    double c = 0.5 * (R[0] + R[4] + R[8] - 1.0);
+    double th = atan2(s, c);
+    if (th < 1e-4) {
+        double f = 1.0 + th * th / 6.0;           /* th / sin th */
+        w[0] = f * vx; w[1] = f * vy; w[2] = f * vz;
+    } else if (M_PI - th > 1e-4) {
+        double f = th / s;
+        w[0] = f * vx; w[1] = f * vy; w[2] = f * vz;
+    } else {
+        /* near pi: the symmetric part gives (R + R^T) / 2 - cos(t) I = (1 - cos t) a a^T;
+         * its column of largest diagonal entry is parallel to the axis a, and the
+         * antisymmetric part fixes the sign */
+        double Bm[9];
+        for (int r = 0; r < 3; ++r)
+            for (int q = 0; q < 3; ++q) Bm[r * 3 + q] = 0.5 * (R[r * 3 + q] + R[q * 3 + r]) - (r == q ? c : 0.0);
+        int k = 0;
+        for (int q = 1; q < 3; ++q) if (Bm[q * 4] > Bm[k * 4]) k = q;
+        double a[3];
+        for (int q = 0; q < 3; ++q) a[q] = Bm[q * 3 + k];
+        double na = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+        double sg = (a[0] * vx + a[1] * vy + a[2] * vz) < 0.0 ? -1.0 : 1.0;
+        for (int q = 0; q < 3; ++q) w[q] = sg * th * a[q] / na;
+    }
+}
+
+/* Right Jacobian of SO(3): Jr(w) = I - B W + C W^2 (Exp(w + d) ~= Exp(w) Exp(Jr d)). */
+void lbaref_so3_jr(const double w[3], double Jr[9]) {
+    double th = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+    double A, B, C, W[9], W2[9];
+    so3_coeffs(th, &A, &B, &C);
+    hat(w, W);
+    matmul(W, W, W2, 3, 3, 3);
+    for (int i = 0; i < 9; ++i) Jr[i] = ((i % 4 == 0) ? 1.0 : 0.0) - B * W[i] + C * W2[i];
+}
+
+/* Its inverse: Jr^-1(w) = I + W / 2 + D W^2, D = 1/t^2 - (1 + cos t) / (2 t sin t). */
+void lbaref_so3_jr_inv(const double w[3], double Jri[9]) {
+    double th = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+    double D, W[9], W2[9];
+    if (th < 1e-2) {
+        double t2 = th * th;
+        D = 1.0 / 12.0 + t2 / 720.0 + t2 * t2 / 30240.0;
+    } else {
+        D = 1.0 / (th * th) - (1.0 + cos(th)) / (2.0 * th * sin(th));
+    }
+    hat(w, W);
+    matmul(W, W, W2, 3, 3, 3);
+    for (int i = 0; i < 9; ++i) Jri[i] = ((i % 4 == 0) ? 1.0 : 0.0) + 0.5 * W[i] + D * W2[i];
+}
+
+static void transpose3(const double *A, double *At) {
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) At[c * 3 + r] = A[r * 3 + c];
+}
+
+/* body rotation and position of a keyframe from its camera pose */
+static void body_pose(const double *T, const double *T_cb, double Rb[9], double pb[3]) {
+    double Rcw[9], RcwT[9], Rcb[9], d[3];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            Rcw[r * 3 + c] = T[r * 4 + c];
+            Rcb[r * 3 + c] = T_cb[r * 4 + c];
+        }
+    transpose3(Rcw, RcwT);
+    matmul(RcwT, Rcb, Rb, 3, 3, 3);
+    for (int q = 0; q < 3; ++q) d[q] = T_cb[q * 4 + 3] - T[q * 4 + 3];
+    matmul(RcwT, d, pb, 3, 3, 1);
+}
+
+/* intermediate quantities of measurement e at the states */
+typedef struct {
+    double Ri[9], Rj[9], pi[3], pj[3];
+    double dbg[3], dba[3], E[9], u[3], w[3], r[15];
+} vi_eval_t;
+
+static void vi_eval(const ref_inertial *I, int e, const double *T, const double *V, const double *BG,
+                    const double *BA, vi_eval_t *q) {
+    int i = I->edge_i[e], j = I->edge_j[e];
+    double dt = I->dt[e];
+    body_pose(T + 12 * i, I->T_cb, q->Ri, q->pi);
+    body_pose(T + 12 * j, I->T_cb, q->Rj, q->pj);
+    for (int a = 0; a < 3; ++a) {
+        q->dbg[a] = BG[3 * i + a] - I->bg_bar[3 * e + a];
+        q->dba[a] = BA[3 * i + a] - I->ba_bar[3 * e + a];
+    }
+    /* rotation: E = (dR Exp(J_Rg dbg))^T R_i^T R_j */
+    double phi[3], Eb[9], dRc[9], dRcT[9], RiT[9], RiTRj[9];
+    matmul(I->J_Rg + 9 * e, q->dbg, phi, 3, 3, 1);
+    so3_exp(phi, Eb);
+    matmul(I->dR + 9 * e, Eb, dRc, 3, 3, 3);
+    transpose3(dRc, dRcT);
+    transpose3(q->Ri, RiT);
+    matmul(RiT, q->Rj, RiTRj, 3, 3, 3);
+    matmul(dRcT, RiTRj, q->E, 3, 3, 3);
+    lbaref_so3_log(q->E, q->r);
+    /* velocity and position */
+    double Ru[3], Rw[3], a1[3], a2[3], b1[3], b2[3];
+    for (int a = 0; a < 3; ++a) {
+        q->u[a] = V[3 * j + a] - V[3 * i + a] - I->g[a] * dt;
+        q->w[a] = q->pj[a] - q->pi[a] - V[3 * i + a] * dt - 0.5 * I->g[a] * dt * dt;
+    }
+    matmul(RiT, q->u, Ru, 3, 3, 1);
+    matmul(RiT, q->w, Rw, 3, 3, 1);
+    matmul(I->J_vg + 9 * e, q->dbg, a1, 3, 3, 1);
+    matmul(I->J_va + 9 * e, q->dba, a2, 3, 3, 1);
+    matmul(I->J_pg + 9 * e, q->dbg, b1, 3, 3, 1);
+    matmul(I->J_pa + 9 * e, q->dba, b2, 3, 3, 1);
+    for (int a = 0; a < 3; ++a) {
+        q->r[3 + a] = Ru[a] - (I->dv[3 * e + a] + a1[a] + a2[a]);
+        q->r[6 + a] = Rw[a] - (I->dp[3 * e + a] + b1[a] + b2[a]);
+        q->r[9 + a] = BG[3 * j + a] - BG[3 * i + a];
+        q->r[12 + a] = BA[3 * j + a] - BA[3 * i + a];
+    }
+}
+
+static double vi_edge_cost(const ref_inertial *I, int e, const double r[15]) {
+    double c = 0.0;
+    for (int a = 0; a < 9; ++a) {
+        double acc = 0.0;
+        for (int b = 0; b < 9; ++b) acc += I->info[81 * e + a * 9 + b] * r[b];
+        c += r[a] * acc;
+    }
+    double g2 = 0.0, a2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        g2 += r[9 + a] * r[9 + a];
+        a2 += r[12 + a] * r[12 + a];
+    }
+    return c + I->info_bg[e] * g2 + I->info_ba[e] * a2;
+}
+
+void lbaref_vi_residual(const ref_inertial *I, int e, const double *T, const double *V, const double *BG,
+                        const double *BA, double r[15]) {
+    vi_eval_t q;
+    vi_eval(I, e, T, V, BG, BA, &q);
+    memcpy(r, q.r, sizeof(q.r));
+}
+
+double lbaref_vi_cost(const ref_inertial *I, const double *T, const double *V, const double *BG,
+                      const double *BA) {
+    double F = 0.0;
+    for (int e = 0; e < I->n_edges; ++e) {
+        vi_eval_t q;
+        vi_eval(I, e, T, V, BG, BA, &q);
+        F += vi_edge_cost(I, e, q.r);
+    }
+    return F;
+}
+
+/* Jacobian (15 x 30, row-major) of the residual of measurement e with respect to the
+ * perturbations (twist, dv, dbg, dba) of keyframe i (columns 0-14) and keyframe j
+ * (columns 15-29).  Body-frame perturbations first: the left twist (w, u) of T_cw turns
+ * the body rotation by -R_cb^T w (on the right) and moves the body position by
+ * R_cw^T ([t_cb]x w - u); then the standard preintegration derivatives. */
+void lbaref_vi_jacobian(const ref_inertial *I, int e, const double *T, const double *V, const double *BG,
+                        const double *BA, double J[450]) {
+    vi_eval_t q;
+    vi_eval(I, e, T, V, BG, BA, &q);
+    double dt = I->dt[e];
+    /* blocks per residual row group and body variable: th_i, p_i, v_i, bg_i, ba_i,
+     * th_j, p_j, v_j, bg_j, ba_j (15 x 3 each) */
+    double Bk[10][45];
+    memset(Bk, 0, sizeof(Bk));
+#define SETB(blk, row, M9) do { for (int rr = 0; rr < 3; ++rr) for (int cc = 0; cc < 3; ++cc) \
+        Bk[blk][((row) + rr) * 3 + cc] = (M9)[rr * 3 + cc]; } while (0)
+    double Jri[9], RjT[9], RjTRi[9], tmp[9], RiT[9], mRiT[9], I3[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1}, mI3[9];
+    lbaref_so3_jr_inv(q.r, Jri);
+    transpose3(q.Rj, RjT);
+    transpose3(q.Ri, RiT);
+    for (int a = 0; a < 9; ++a) {
+        mRiT[a] = -RiT[a];
+        mI3[a] = -I3[a];
+    }
+    /* r_R */
+    matmul(RjT, q.Ri, RjTRi, 3, 3, 3);
+    matmul(Jri, RjTRi, tmp, 3, 3, 3);
+    for (int a = 0; a < 9; ++a) tmp[a] = -tmp[a];
+    SETB(0, 0, tmp);
+    SETB(5, 0, Jri);
+    {
+        double phi[3], Jr[9], ET[9], M1[9], M2[9], M3[9];
+        matmul(I->J_Rg + 9 * e, q.dbg, phi, 3, 3, 1);
+        lbaref_so3_jr(phi, Jr);
+        transpose3(q.E, ET);
+        matmul(Jri, ET, M1, 3, 3, 3);
+        matmul(M1, Jr, M2, 3, 3, 3);
+        matmul(M2, I->J_Rg + 9 * e, M3, 3, 3, 3);
+        for (int a = 0; a < 9; ++a) M3[a] = -M3[a];
+        SETB(3, 0, M3);
+    }
+    /* r_v */
+    {
+        double Ru[3], H[9], M[9];
+        matmul(RiT, q.u, Ru, 3, 3, 1);
+        hat(Ru, H);
+        SETB(0, 3, H);
+        SETB(2, 3, mRiT);
+        SETB(7, 3, RiT);
+        for (int a = 0; a < 9; ++a) M[a] = -I->J_vg[9 * e + a];
+        SETB(3, 3, M);
+        for (int a = 0; a < 9; ++a) M[a] = -I->J_va[9 * e + a];
+        SETB(4, 3, M);
+    }
+    /* r_p */
+    {
+        double Rw[3], H[9], M[9];
+        matmul(RiT, q.w, Rw, 3, 3, 1);
+        hat(Rw, H);
+        SETB(0, 6, H);
+        SETB(1, 6, mRiT);
+        SETB(6, 6, RiT);
+        for (int a = 0; a < 9; ++a) M[a] = -RiT[a] * dt;
+        SETB(2, 6, M);
+        for (int a = 0; a < 9; ++a) M[a] = -I->J_pg[9 * e + a];
+        SETB(3, 6, M);
+        for (int a = 0; a < 9; ++a) M[a] = -I->J_pa[9 * e + a];
+        SETB(4, 6, M);
+    }
+    /* bias random walks */
+    SETB(3, 9, mI3);
+    SETB(8, 9, I3);
+    SETB(4, 12, mI3);
+    SETB(9, 12, I3);
+#undef SETB
+    /* chain to the camera twist of each keyframe, assemble 15 x 30 */
+    memset(J, 0, sizeof(double) * 450);
+    double RcbT[9], Rcb[9], tcb[3], tx[9];
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) Rcb[r * 3 + c] = I->T_cb[r * 4 + c];
+        tcb[r] = I->T_cb[r * 4 + 3];
+    }
+    transpose3(Rcb, RcbT);
+    hat(tcb, tx);
+    for (int side = 0; side < 2; ++side) {
+        int k = side == 0 ? I->edge_i[e] : I->edge_j[e];
+        const double *Tk = T + 12 * k;
+        double Rcw[9], RcwT[9], Ptw[9];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) Rcw[r * 3 + c] = Tk[r * 4 + c];
+        transpose3(Rcw, RcwT);
+        matmul(RcwT, tx, Ptw, 3, 3, 3);                 /* d p / d w = R_cw^T [t_cb]x */
+        const double *Bth = Bk[5 * side + 0], *Bp = Bk[5 * side + 1];
+        for (int row = 0; row < 15; ++row) {
+            double *Jr = J + row * 30 + 15 * side;
+            for (int c = 0; c < 3; ++c) {
+                double aw = 0.0, au = 0.0;
+                for (int m = 0; m < 3; ++m) {
+                    aw += Bth[row * 3 + m] * (-RcbT[m * 3 + c]) + Bp[row * 3 + m] * Ptw[m * 3 + c];
+                    au += Bp[row * 3 + m] * (-RcwT[m * 3 + c]);
+                }
+                Jr[c] = aw;
+                Jr[3 + c] = au;
+            }
+            for (int blk = 2; blk < 5; ++blk)
+                for (int c = 0; c < 3; ++c) Jr[6 + 3 * (blk - 2) + c] = Bk[5 * side + blk][row * 3 + c];
+        }
+    }
+}
+
+/* inertial normal equations over the 15 Kopt unknowns: H (n x n, added), b (added),
+ * b = -J^T Info r; returns the inertial cost */
+static double vi_linearize(const ref_inertial *I, const int *opt, int n, const double *T, const double *V,
+                           const double *BG, const double *BA, double *H, double *b) {
+    double F = 0.0;
+    for (int e = 0; e < I->n_edges; ++e) {
+        vi_eval_t q;
+        vi_eval(I, e, T, V, BG, BA, &q);
+        F += vi_edge_cost(I, e, q.r);
+        double J[450], Om[225];
+        lbaref_vi_jacobian(I, e, T, V, BG, BA, J);
+        memset(Om, 0, sizeof(Om));
+        for (int a = 0; a < 9; ++a)
+            for (int c = 0; c < 9; ++c) Om[a * 15 + c] = I->info[81 * e + a * 9 + c];
+        for (int a = 9; a < 12; ++a) Om[a * 15 + a] = I->info_bg[e];
+        for (int a = 12; a < 15; ++a) Om[a * 15 + a] = I->info_ba[e];
+        double OJ[450], Or[15];
+        matmul(Om, J, OJ, 15, 15, 30);
+        matmul(Om, q.r, Or, 15, 15, 1);
+        int col0[2] = {opt[I->edge_i[e]], opt[I->edge_j[e]]};
+        for (int sa = 0; sa < 2; ++sa) {
+            if (col0[sa] < 0) continue;
+            for (int a = 0; a < 15; ++a) {
+                int ga = 15 * col0[sa] + a, ca = 15 * sa + a;
+                double g = 0.0;
+                for (int m = 0; m < 15; ++m) g += J[m * 30 + ca] * Or[m];
+                b[ga] -= g;
+                for (int sc = 0; sc < 2; ++sc) {
+                    if (col0[sc] < 0) continue;
+                    for (int c = 0; c < 15; ++c) {
+                        int gc = 15 * col0[sc] + c, cc = 15 * sc + c;
+                        double acc = 0.0;
+                        for (int m = 0; m < 15; ++m) acc += J[m * 30 + ca] * OJ[m * 30 + cc];
+                        H[ga * n + gc] += acc;
+                    }
+                }
+            }
+        }
+    }
+    return F;
+}
+
+/* Damped step of the visual-inertial system: the visual reduced system (6 Kopt) placed in
+ * the pose rows of the 15 Kopt system, the inertial blocks and lambda on the velocity and
+ * bias diagonal added, dense Cholesky, then the points back-substituted with the pose
+ * part.  d: 15 Kopt, dl: 3 M.  Returns 0, or 1 if a factorisation failed. */
+static int vi_step(const ref_problem *P, const blocks_t *B, const uint8_t *active, double lambda,
+                   const double *Hi, const double *bi, double *d, double *dl) {
+    int nv = 6 * B->Kopt, n = 15 * B->Kopt;
+    double *Sv = (double *)malloc(sizeof(double) * ((size_t)nv * nv + 1));
+    double *rv = (double *)malloc(sizeof(double) * (nv + 1));
+    double *S = (double *)malloc(sizeof(double) * ((size_t)n * n + 1));
+    double *dp = (double *)malloc(sizeof(double) * (nv + 1));
+    int fail = reduced_system(P, B, active, lambda, Sv, rv);
+    if (!fail) {
+        for (int a = 0; a < n; ++a) {
+            d[a] = bi[a];
+            for (int c = 0; c < n; ++c) S[a * n + c] = Hi[a * n + c];
+            if (a % 15 >= 6) S[a * n + a] += lambda;
+        }
+        for (int ka = 0; ka < B->Kopt; ++ka)
+            for (int a = 0; a < 6; ++a) {
+                d[15 * ka + a] += rv[6 * ka + a];
+                for (int kc = 0; kc < B->Kopt; ++kc)
+                    for (int c = 0; c < 6; ++c) S[(15 * ka + a) * n + 15 * kc + c] += Sv[(6 * ka + a) * nv + 6 * kc + c];
+            }
+        if (n > 0) {
+            fail = lbaref_cholesky(n, S);
+            if (!fail) chol_solve(n, S, d);
+        }
+    }
+    if (!fail) {
+        for (int ka = 0; ka < B->Kopt; ++ka)
+            for (int a = 0; a < 6; ++a) dp[6 * ka + a] = d[15 * ka + a];
+        fail = back_substitute(P, B, active, lambda, dp, dl);
+    }
+    free(Sv); free(rv); free(S); free(dp);
+    return fail;
+}
+
+typedef struct {
+    double *V, *BG, *BA;
+} vi_states_t;
+
+static int vi_lm_round(const ref_problem *P, const ref_options *O, const ref_inertial *I, int round, int iters,
+                       const uint8_t *active, int robust, double *T, double *X, vi_states_t *S, blocks_t *B,
+                       double *F_out, double *lambda_out, int *trials_total, int *terminated, ref_logrec *log,
+                       int log_cap, int *log_n) {
+    int n = 15 * B->Kopt, K = B->K;
+    double *Hi = (double *)malloc(sizeof(double) * ((size_t)n * n + 1));
+    double *bi = (double *)malloc(sizeof(double) * (n + 1));
+    double *d = (double *)malloc(sizeof(double) * (n + 1));
+    double *dl = (double *)malloc(sizeof(double) * (3 * B->M + 1));
+    double *T2 = (double *)malloc(sizeof(double) * (12 * K + 1));
+    double *X2 = (double *)malloc(sizeof(double) * (3 * B->M + 1));
+    double *dp = (double *)malloc(sizeof(double) * (6 * B->Kopt + 1));
+    double *V2 = (double *)malloc(sizeof(double) * (3 * K + 1));
+    double *G2 = (double *)malloc(sizeof(double) * (3 * K + 1));
+    double *A2 = (double *)malloc(sizeof(double) * (3 * K + 1));
+    double F = 0.0, lambda = 0.0, nu = 2.0;
+    int done = 0;
+    *terminated = 0;
+    for (int it = 0; it < iters; ++it) {
+        /* linearise both parts at the current state */
+        linearize(P, O, T, X, active, robust, B);
+        memset(Hi, 0, sizeof(double) * n * n);
+        memset(bi, 0, sizeof(double) * n);
+        double Fi = vi_linearize(I, B->opt, n, T, S->V, S->BG, S->BA, Hi, bi);
+        if (it == 0) {
+            F = B->F + Fi;
+            /* largest diagonal entry of the whole Gauss-Newton matrix */
+            double md = 0.0;
+            for (int k = 0; k < B->Kopt; ++k)
+                for (int a = 0; a < 15; ++a) {
+                    double v = Hi[(15 * k + a) * n + 15 * k + a];
+                    if (a < 6) v += B->Hpp[k * 36 + a * 7];
+                    md = fmax(md, v);
+                }
+            for (int j = 0; j < 3 * B->M; ++j) md = fmax(md, B->Hll[(j / 3) * 9 + (j % 3) * 4]);
+            lambda = lbaref_initial_damping(O->tau, md);
+            nu = 2.0;
+        }
+        int accepted = 0;
+        for (int tr = 0; tr < O->max_trials; ++tr) {
+            ++*trials_total;
+            int fail = vi_step(P, B, active, lambda, Hi, bi, d, dl);
+            double F2 = NAN, gain = NAN;
+            if (!fail) {
+                for (int k = 0; k < B->Kopt; ++k)
+                    for (int a = 0; a < 6; ++a) dp[6 * k + a] = d[15 * k + a];
+                retract(B, T, X, dp, dl, T2, X2);
+                for (int k = 0; k < K; ++k) {
+                    int ok = B->opt[k];
+                    for (int a = 0; a < 3; ++a) {
+                        V2[3 * k + a] = S->V[3 * k + a] + (ok >= 0 ? d[15 * ok + 6 + a] : 0.0);
+                        G2[3 * k + a] = S->BG[3 * k + a] + (ok >= 0 ? d[15 * ok + 9 + a] : 0.0);
+                        A2[3 * k + a] = S->BA[3 * k + a] + (ok >= 0 ? d[15 * ok + 12 + a] : 0.0);
+                    }
+                }
+                F2 = lbaref_cost(P, O, T2, X2, active, robust) + lbaref_vi_cost(I, T2, V2, G2, A2);
+                /* predicted decrease d^T (lambda d + b), b = visual + inertial gradient */
+                double den = 0.0;
+                for (int k = 0; k < B->Kopt; ++k)
+                    for (int a = 0; a < 15; ++a) {
+                        double g = bi[15 * k + a] + (a < 6 ? B->bp[6 * k + a] : 0.0);
+                        double x = d[15 * k + a];
+                        den += x * (lambda * x + g);
+                    }
+                for (int q = 0; q < 3 * B->M; ++q) den += dl[q] * (lambda * dl[q] + B->bl[q]);
+                gain = (F - F2) / den;
+            }
+            int acc = !fail && isfinite(F2) && isfinite(gain) && gain > 0.0;
+            if (log && *log_n < log_cap) {
+                ref_logrec *L = &log[(*log_n)++];
+                L->round = round; L->iter = it; L->trial = tr; L->accepted = acc;
+                L->solve_ok = !fail; L->pad = 0;
+                L->lambda = lambda; L->F = F; L->F_trial = F2; L->gain = gain;
+            }
+            lbaref_damping_update(gain, acc, &lambda, &nu);
+            if (acc) {
+                memcpy(T, T2, sizeof(double) * 12 * K);
+                memcpy(X, X2, sizeof(double) * 3 * B->M);
+                memcpy(S->V, V2, sizeof(double) * 3 * K);
+                memcpy(S->BG, G2, sizeof(double) * 3 * K);
+                memcpy(S->BA, A2, sizeof(double) * 3 * K);
+                F = F2;
+                accepted = 1;
+                break;
+            }
+        }
+        if (!accepted) {
+            *terminated = 1;
+            break;
+        }
+        ++done;
+    }
+    if (iters == 0) F = lbaref_cost(P, O, T, X, active, robust) + lbaref_vi_cost(I, T, S->V, S->BG, S->BA);
+    *F_out = F;
+    lambda_out[0] = lambda;
+    free(Hi); free(bi); free(d); free(dl); free(T2); free(X2); free(dp); free(V2); free(G2); free(A2);
+    return done;
+}
+
+/* Full stereo-inertial solve: the schedule of lbaref_solve (round 1, outlier pass on the
+ * reprojection terms, round 2, final flags) on the joint cost.  V/BG/BA in: n_kf x 3
+ * each, overwritten with the result.  stats as lbaref_solve (costs include the inertial
+ * terms).  Returns 0, or -1 for invalid input. */
+int lbaref_solve_vi(const ref_problem *P, const ref_options *O, const ref_inertial *I, double *T_out,
+                    double *X_out, double *V, double *BG, double *BA, uint8_t *outlier_out, double *stats,
+                    ref_logrec *log, int log_cap, int *log_n) {
+    for (int i = 0; i < P->n_obs; ++i) {
+        if (P->obs_kf[i] < 0 || P->obs_kf[i] >= P->n_kf) return -1;
+        if (P->obs_pt[i] < 0 || P->obs_pt[i] >= P->n_pt) return -1;
+        if (P->obs_oct[i] >= P->n_levels) return -1;
+    }
+    for (int e = 0; e < I->n_edges; ++e)
+        if (I->edge_i[e] < 0 || I->edge_i[e] >= P->n_kf || I->edge_j[e] < 0 || I->edge_j[e] >= P->n_kf ||
+            I->edge_i[e] == I->edge_j[e])
+            return -1;
+    int ln = 0;
+    if (!log_n) log_n = &ln;
+    *log_n = 0;
+    memcpy(T_out, P->T_cw, sizeof(double) * 12 * P->n_kf);
+    memcpy(X_out, P->X_w, sizeof(double) * 3 * P->n_pt);
+    vi_states_t S = {V, BG, BA};
+    blocks_t B;
+    blocks_alloc(&B, P);
+    double F0 = lbaref_cost(P, O, T_out, X_out, NULL, 1) + lbaref_vi_cost(I, T_out, V, BG, BA);
+    double F1 = F0, F2, lam1 = 0.0, lam2 = 0.0;
+    int trials = 0, term1 = 0, term2 = 0;
+    int it1 = vi_lm_round(P, O, I, 1, O->iters_round1, NULL, 1, T_out, X_out, &S, &B, &F1, &lam1, &trials, &term1,
+                          log, log_cap, log_n);
+    uint8_t *active = (uint8_t *)malloc((size_t)P->n_obs + 1);
+    lbaref_flags(P, O, T_out, X_out, outlier_out);
+    for (int i = 0; i < P->n_obs; ++i) active[i] = !outlier_out[i];
+    double F20 = lbaref_cost(P, O, T_out, X_out, active, O->round2_robust) + lbaref_vi_cost(I, T_out, V, BG, BA);
+    int it2 = vi_lm_round(P, O, I, 2, O->iters_round2, active, O->round2_robust, T_out, X_out, &S, &B, &F2, &lam2,
+                          &trials, &term2, log, log_cap, log_n);
+    lbaref_flags(P, O, T_out, X_out, outlier_out);
+    int nout = 0;
+    for (int i = 0; i < P->n_obs; ++i) nout += outlier_out[i];
+    if (stats) {
+        stats[0] = F0; stats[1] = F2; stats[2] = it1; stats[3] = it2; stats[4] = trials;
+        stats[5] = O->iters_round2 > 0 ? lam2 : lam1; stats[6] = term1; stats[7] = term2;
+        stats[8] = nout; stats[9] = F1; stats[10] = F20; stats[11] = B.Kopt;
+    }
+    free(active);
+    blocks_free(&B);
+    return 0;
+}
+
+/* The damped visual-inertial step at a state, for pinning (d: 15 Kopt, dl: 3 M; cost and
+ * largest diagonal entry in Fmd[0], Fmd[1]).  Returns 0 or 1 (factorisation failed). */
+int lbaref_vi_system_step(const ref_problem *P, const ref_options *O, const ref_inertial *I, const double *T,
+                          const double *X, const double *V, const double *BG, const double *BA, double lambda,
+                          double *d, double *dl, double *Fmd) {
+    blocks_t B;
+    blocks_alloc(&B, P);
+    linearize(P, O, T, X, NULL, 1, &B);
+    int n = 15 * B.Kopt;
+    double *Hi = (double *)calloc((size_t)n * n + 1, sizeof(double));
+    double *bi = (double *)calloc(n + 1, sizeof(double));
+    double Fi = vi_linearize(I, B.opt, n, T, V, BG, BA, Hi, bi);
+    Fmd[0] = B.F + Fi;
+    int fail = vi_step(P, &B, NULL, lambda, Hi, bi, d, dl);
+    free(Hi); free(bi);
+    blocks_free(&B);
+    return fail;
 }

@@ -324,3 +324,157 @@ def damping_update(gain: float, accepted: bool, lam: float, nu: float) -> tuple[
     l, n = C.c_double(lam), C.c_double(nu)
     lib().lbaref_damping_update(gain, int(accepted), C.byref(l), C.byref(n))
     return l.value, n.value
+
+
+# ---------------------------------------------------------------------------------------
+# stereo-inertial local bundle adjustment
+# ---------------------------------------------------------------------------------------
+class Inertial(C.Structure):
+    _fields_ = [("n_edges", C.c_int32), ("pad", C.c_int32)] + \
+        [(k, C.c_void_p) for k in ("edge_i", "edge_j", "dt", "dR", "dv", "dp", "J_Rg", "J_vg", "J_va", "J_pg",
+                                   "J_pa", "bg_bar", "ba_bar", "info", "info_bg", "info_ba", "T_cb")] + \
+        [("g", C.c_double * 3)]
+
+
+VI_KEYS = [("edge_i", np.int32, 1), ("edge_j", np.int32, 1), ("dt", np.float64, 1), ("dR", np.float64, 9),
+           ("dv", np.float64, 3), ("dp", np.float64, 3), ("J_Rg", np.float64, 9), ("J_vg", np.float64, 9),
+           ("J_va", np.float64, 9), ("J_pg", np.float64, 9), ("J_pa", np.float64, 9), ("bg_bar", np.float64, 3),
+           ("ba_bar", np.float64, 3), ("info", np.float64, 81), ("info_bg", np.float64, 1),
+           ("info_ba", np.float64, 1)]
+
+
+class _BoundVI:
+    """Keeps the numpy arrays behind an ``Inertial`` alive."""
+
+    def __init__(self, vi: dict):
+        self.arrs = {k: np.ascontiguousarray(vi[k], dtype=dt).reshape(-1) for k, dt, _ in VI_KEYS}
+        self.arrs["T_cb"] = np.ascontiguousarray(vi["T_cb"], dtype=np.float64).reshape(12)
+        n = len(self.arrs["edge_i"])
+        for k, _, m in VI_KEYS:
+            assert self.arrs[k].size == n * m, k
+        self.I = Inertial(n, 0, *[self.arrs[k].ctypes.data for k, _, _ in VI_KEYS],
+                          self.arrs["T_cb"].ctypes.data, (C.c_double * 3)(*[float(x) for x in vi["g"]]))
+
+
+def _vi_lib():
+    L = lib()
+    if not getattr(L, "_vi_ready", False):
+        dp, vp = C.POINTER(C.c_double), C.c_void_p
+        IP, P, O = C.POINTER(Inertial), C.POINTER(Problem), C.POINTER(Options)
+        L.lbaref_so3_log.argtypes = [dp, dp]
+        L.lbaref_so3_jr.argtypes = [dp, dp]
+        L.lbaref_so3_jr_inv.argtypes = [dp, dp]
+        L.lbaref_vi_residual.argtypes = [IP, C.c_int, vp, vp, vp, vp, vp]
+        L.lbaref_vi_jacobian.argtypes = [IP, C.c_int, vp, vp, vp, vp, vp]
+        L.lbaref_vi_cost.argtypes = [IP, vp, vp, vp, vp]
+        L.lbaref_vi_cost.restype = C.c_double
+        L.lbaref_solve_vi.argtypes = [P, O, IP, vp, vp, vp, vp, vp, vp, vp, C.POINTER(LogRec), C.c_int,
+                                      C.POINTER(C.c_int)]
+        L.lbaref_solve_vi.restype = C.c_int
+        L.lbaref_vi_system_step.argtypes = [P, O, IP, vp, vp, vp, vp, vp, C.c_double, vp, vp, vp]
+        L.lbaref_vi_system_step.restype = C.c_int
+        L._vi_ready = True
+    return L
+
+
+def _d(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a if shape is None else a.reshape(shape)
+
+
+def so3_log(R) -> np.ndarray:
+    R = _d(R, 9)
+    w = np.zeros(3)
+    _vi_lib().lbaref_so3_log(_p(R, C.c_double), _p(w, C.c_double))
+    return w
+
+
+def so3_jr(w) -> np.ndarray:
+    w = _d(w, 3)
+    J = np.zeros(9)
+    _vi_lib().lbaref_so3_jr(_p(w, C.c_double), _p(J, C.c_double))
+    return J.reshape(3, 3)
+
+
+def so3_jr_inv(w) -> np.ndarray:
+    w = _d(w, 3)
+    J = np.zeros(9)
+    _vi_lib().lbaref_so3_jr_inv(_p(w, C.c_double), _p(J, C.c_double))
+    return J.reshape(3, 3)
+
+
+def _vi_states(vi, T=None, V=None, BG=None, BA=None, w=None):
+    T = _d(w["T_cw"] if T is None else T, (-1, 12))
+    V = _d(vi["v"] if V is None else V, (-1, 3))
+    BG = _d(vi["bg"] if BG is None else BG, (-1, 3))
+    BA = _d(vi["ba"] if BA is None else BA, (-1, 3))
+    return T, V, BG, BA
+
+
+def vi_residual(w: dict, vi: dict, e: int, T=None, V=None, BG=None, BA=None) -> np.ndarray:
+    bv = _BoundVI(vi)
+    T, V, BG, BA = _vi_states(vi, T, V, BG, BA, w)
+    r = np.zeros(15)
+    _vi_lib().lbaref_vi_residual(C.byref(bv.I), int(e), T.ctypes.data, V.ctypes.data, BG.ctypes.data,
+                                 BA.ctypes.data, r.ctypes.data)
+    return r
+
+
+def vi_jacobian(w: dict, vi: dict, e: int, T=None, V=None, BG=None, BA=None) -> np.ndarray:
+    bv = _BoundVI(vi)
+    T, V, BG, BA = _vi_states(vi, T, V, BG, BA, w)
+    J = np.zeros(450)
+    _vi_lib().lbaref_vi_jacobian(C.byref(bv.I), int(e), T.ctypes.data, V.ctypes.data, BG.ctypes.data,
+                                 BA.ctypes.data, J.ctypes.data)
+    return J.reshape(15, 30)
+
+
+def vi_cost(w: dict, vi: dict, T=None, V=None, BG=None, BA=None) -> float:
+    bv = _BoundVI(vi)
+    T, V, BG, BA = _vi_states(vi, T, V, BG, BA, w)
+    return _vi_lib().lbaref_vi_cost(C.byref(bv.I), T.ctypes.data, V.ctypes.data, BG.ctypes.data, BA.ctypes.data)
+
+
+def solve_vi(w: dict, vi: dict, log_cap: int = 4096, **opts) -> dict:
+    """The two-round stereo-inertial LM on one window (states v, bg, ba from vi)."""
+    b = _Bound(w)
+    bv = _BoundVI(vi)
+    O = options(**opts)
+    T = np.zeros((b.K, 12))
+    X = np.zeros((b.M, 3))
+    V = _d(vi["v"], (-1, 3)).copy()
+    BG = _d(vi["bg"], (-1, 3)).copy()
+    BA = _d(vi["ba"], (-1, 3)).copy()
+    fl = np.zeros(b.N, dtype=np.uint8)
+    st = np.zeros(12)
+    log = (LogRec * log_cap)()
+    nlog = C.c_int(0)
+    rc = _vi_lib().lbaref_solve_vi(C.byref(b.P), C.byref(O), C.byref(bv.I), T.ctypes.data, X.ctypes.data,
+                                   V.ctypes.data, BG.ctypes.data, BA.ctypes.data, fl.ctypes.data, st.ctypes.data,
+                                   log, log_cap, C.byref(nlog))
+    if rc != 0:
+        raise ValueError("oracle rejected the problem")
+    recs = [dict(round=r.round, iter=r.iter, trial=r.trial, accepted=bool(r.accepted),
+                 solve_ok=bool(r.solve_ok), lam=r.lam, F=r.F, F_trial=r.F_trial, gain=r.gain)
+            for r in log[: nlog.value]]
+    names = ["F_initial", "F_final", "iters_r1", "iters_r2", "trials", "lambda", "term_r1",
+             "term_r2", "n_outliers", "F_end_r1", "F_start_r2", "Kopt"]
+    return dict(T=T, X=X, V=V, BG=BG, BA=BA, outlier=fl.astype(bool), stats=dict(zip(names, st.tolist())),
+                log=recs)
+
+
+def vi_system_step(w: dict, vi: dict, lam: float, T=None, X=None, V=None, BG=None, BA=None, **opts) -> dict:
+    """The damped visual-inertial step at a state (no outlier mask, robust): d (15 Kopt)
+    and the point step dl (M, 3)."""
+    b = _Bound(w)
+    bv = _BoundVI(vi)
+    O = options(**opts)
+    T, V, BG, BA = _vi_states(vi, T, V, BG, BA, w)
+    X = _d(w["X"] if X is None else X, (-1, 3))
+    d = np.zeros(15 * b.Kopt)
+    dl = np.zeros((b.M, 3))
+    Fmd = np.zeros(2)
+    rc = _vi_lib().lbaref_vi_system_step(C.byref(b.P), C.byref(O), C.byref(bv.I), T.ctypes.data, X.ctypes.data,
+                                         V.ctypes.data, BG.ctypes.data, BA.ctypes.data, float(lam), d.ctypes.data,
+                                         dl.ctypes.data, Fmd.ctypes.data)
+    return dict(ok=rc == 0, d=d, dl=dl, F=Fmd[0])

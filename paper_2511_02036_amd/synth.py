@@ -526,3 +526,115 @@ def fusion_points(store: dict, seed: int = 6, n_cur: int = 64, n_nbr: int = 20, 
     }
     q = (np.array(q_p0, dtype=np.int32), np.array(q_p1, dtype=np.int32), np.array(q_nbr, dtype=np.int32))
     return pts, q
+
+
+# ----------------------------------------------------------------------------------------
+# stereo-inertial windows
+# ----------------------------------------------------------------------------------------
+GRAVITY = np.array([0.0, 9.81, 0.0])   # world frame of the walks: y points down
+# body (IMU) to camera: a small fixed rotation and a lever arm of a few centimetres
+_R_CB = expm(np.array([[0.0, -0.03, -0.01], [0.03, 0.0, -0.02], [0.01, 0.02, 0.0]]))
+T_CB = np.concatenate([_R_CB, np.array([[0.05], [-0.02], [0.01]])], axis=1)
+
+
+def _so3(w):
+    return expm(np.array([[0.0, -w[2], w[1]], [w[2], 0.0, -w[0]], [-w[1], w[0], 0.0]]))
+
+
+def vi_window(seed: int, K: int = 15, n_fixed: int = 5, M: int = 6000, nobs: tuple[int, int] = (8, 8),
+              stereo_p: float = 0.7, walk_length: float = 4.0, noise: bool = True) -> tuple[dict, dict]:
+    """A stereo-inertial window: the visual window of ``make_window`` (walk trajectory) and,
+    between consecutive keyframes, a preintegrated inertial measurement consistent with the
+    true body motion.
+
+    Body frame: camera pose T_cw and body-to-camera T_CB give the body rotation
+    R = R_cw^T R_cb and position p = R_cw^T (t_cb - t_cw).  Keyframes are dt ~ U[0.2, 0.3] s
+    apart; true velocities are central differences of the body positions over time (one-
+    sided at the ends); true biases bg ~ N(0, 2e-3) rad/s and ba ~ N(0, 2e-2) m/s^2 per axis
+    at the first keyframe, then a random walk of N(0, 1e-4) / N(0, 1e-3) per edge.  Each
+    measurement carries the biases it was integrated with (truth + N(0, 1e-3) / N(0, 1e-2))
+    and bias Jacobians near their first-order values (J_Rg ~ -dt I, J_va ~ -dt I,
+    J_pa ~ -dt^2/2 I, J_vg and J_pg small), plus N(0, 0.05 scale) perturbations; its
+    (dR, dv, dp) give a zero inertial residual at the true states, then (noise only) are
+    perturbed by a draw of the measurement's own covariance.  Information: the inverse of a
+    correlated 9x9 covariance with standard deviations 2e-3 rad, 5e-3 m/s, 1e-3 m; bias
+    random-walk information 1 / (1e-4^2 dt) and 1 / (1e-3^2 dt).  Optimisable keyframes
+    start with velocities + N(0, 0.05) m/s, biases + N(0, 1e-3) / N(0, 1e-2).
+
+    Draw order after the visual window (same generator): time steps, biases at the first
+    keyframe, bias walks, per edge (integration biases, Jacobian perturbations, covariance
+    factor, measurement noise), velocity and bias perturbations."""
+    rng = np.random.default_rng(seed)
+    w = make_window(rng, trajectory="walk", K=K, n_fixed=n_fixed, M=M, nobs=nobs, stereo_p=stereo_p,
+                    walk_length=walk_length, noise=noise)
+    T = w["T_true"].reshape(K, 3, 4)
+    Rcb, tcb = T_CB[:, :3], T_CB[:, 3]
+    Rb = np.einsum("kji,jl->kil", T[:, :, :3], Rcb)               # R_cw^T R_cb
+    pb = np.einsum("kji,kj->ki", T[:, :, :3], tcb[None, :] - T[:, :, 3])
+    dts = rng.uniform(0.2, 0.3, size=K - 1)
+    t = np.concatenate([[0.0], np.cumsum(dts)])
+    v = np.empty((K, 3))
+    for k in range(K):
+        a, b = max(k - 1, 0), min(k + 1, K - 1)
+        v[k] = (pb[b] - pb[a]) / (t[b] - t[a])
+    bg = np.empty((K, 3))
+    ba = np.empty((K, 3))
+    bg[0] = rng.normal(0.0, 2e-3, 3)
+    ba[0] = rng.normal(0.0, 2e-2, 3)
+    steps_g = rng.normal(0.0, 1e-4, (K - 1, 3))
+    steps_a = rng.normal(0.0, 1e-3, (K - 1, 3))
+    for k in range(1, K):
+        bg[k] = bg[k - 1] + (steps_g[k - 1] if noise else 0.0)
+        ba[k] = ba[k - 1] + (steps_a[k - 1] if noise else 0.0)
+    sig = np.array([2e-3] * 3 + [5e-3] * 3 + [1e-3] * 3)
+    E = dict(edge_i=[], edge_j=[], dt=[], dR=[], dv=[], dp=[], J_Rg=[], J_vg=[], J_va=[], J_pg=[], J_pa=[],
+             bg_bar=[], ba_bar=[], info=[], info_bg=[], info_ba=[])
+    I3 = np.eye(3)
+    for e in range(K - 1):
+        i, j, dt = e, e + 1, dts[e]
+        bgb = bg[i] + rng.normal(0.0, 1e-3, 3)
+        bab = ba[i] + rng.normal(0.0, 1e-2, 3)
+        pert = rng.normal(0.0, 0.05, (5, 3, 3))
+        J_Rg = -dt * (I3 + pert[0])
+        J_vg = 0.5 * dt * dt * pert[1]
+        J_va = -dt * (I3 + pert[2])
+        J_pg = dt ** 3 / 6.0 * pert[3]
+        J_pa = -0.5 * dt * dt * (I3 + pert[4])
+        Lf = np.diag(sig) @ (np.eye(9) + 0.1 * np.tril(rng.normal(size=(9, 9)), -1))
+        cov = Lf @ Lf.T
+        n9 = Lf @ rng.normal(size=9) if noise else np.zeros(9)
+        dbg, dba = bg[i] - bgb, ba[i] - bab
+        # measurements that zero the residual at the true states, then the noise
+        dR = Rb[i].T @ Rb[j] @ _so3(J_Rg @ dbg).T
+        dv = Rb[i].T @ (v[j] - v[i] - GRAVITY * dt) - J_vg @ dbg - J_va @ dba
+        dp = Rb[i].T @ (pb[j] - pb[i] - v[i] * dt - 0.5 * GRAVITY * dt * dt) - J_pg @ dbg - J_pa @ dba
+        dR = dR @ _so3(-n9[:3])
+        dv = dv + n9[3:6]
+        dp = dp + n9[6:9]
+        for k_, val in (("edge_i", i), ("edge_j", j), ("dt", dt), ("dR", dR), ("dv", dv), ("dp", dp),
+                        ("J_Rg", J_Rg), ("J_vg", J_vg), ("J_va", J_va), ("J_pg", J_pg), ("J_pa", J_pa),
+                        ("bg_bar", bgb), ("ba_bar", bab), ("info", np.linalg.inv(cov)),
+                        ("info_bg", 1.0 / (1e-4 ** 2 * dt)), ("info_ba", 1.0 / (1e-3 ** 2 * dt))):
+            E[k_].append(val)
+    vi = {k: np.asarray(x) for k, x in E.items()}
+    vi["edge_i"] = vi["edge_i"].astype(np.int32)
+    vi["edge_j"] = vi["edge_j"].astype(np.int32)
+    vi["T_cb"] = T_CB.copy()
+    vi["g"] = GRAVITY.copy()
+    vi["v_true"], vi["bg_true"], vi["ba_true"] = v.copy(), bg.copy(), ba.copy()
+    v0, bg0, ba0 = v.copy(), bg.copy(), ba.copy()
+    dv0 = rng.normal(0.0, 0.05, (K, 3))
+    dg0 = rng.normal(0.0, 1e-3, (K, 3))
+    da0 = rng.normal(0.0, 1e-2, (K, 3))
+    opt = w["fixed"] == 0
+    v0[opt] += dv0[opt]
+    bg0[opt] += dg0[opt]
+    ba0[opt] += da0[opt]
+    vi["v"], vi["bg"], vi["ba"] = v0, bg0, ba0
+    return w, vi
+
+
+def vi_stereo(seed: int = 7, noise: bool = True) -> tuple[dict, dict]:
+    """Stereo-inertial window: 10 optimisable + 5 fixed keyframes on a 4 m walk, 6,000
+    points, 8 observations per point (70% stereo): a reduced system of 150 unknowns."""
+    return vi_window(seed, K=15, n_fixed=5, M=6000, nobs=(8, 8), stereo_p=0.7, walk_length=4.0, noise=noise)
