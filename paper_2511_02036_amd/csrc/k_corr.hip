@@ -169,9 +169,18 @@ __device__ void corr_flush(const CorrArgs &a, const double *geo, int ca, int na,
     }
 }
 
-// One block = 4 wavefronts = 128 free keypoints (rows) of cur[q], 32 per wavefront, each
-// wavefront sweeping all free keypoints (columns) of nbr[q] in tiles of 32.
+// One block = 4 wavefronts = 256 free keypoints (rows) of cur[q], two strips of 32 per
+// wavefront, sweeping the free keypoints (columns) of nbr[q] in tiles of 32.  The tile's
+// column descriptors are staged in LDS once for all four wavefronts (8 KB, columns 272
+// bytes apart so that the 16-byte reads of 16 lanes fall in distinct banks), double
+// buffered: tile i + 1 is written to LDS and tile i + 2 loaded from HBM while tile i is
+// multiplied.  Per tile and wavefront: two independent chains of eight MFMAs.
+constexpr int kColPad = 272;
+constexpr int kStrips = 2;
+static_assert(kCorrRows == 4 * 32 * kStrips, "rows per block");
+
 __global__ __launch_bounds__(256) void k_corr_search(CorrArgs a) {
+    __shared__ __align__(16) unsigned char tileB[2][32 * kColPad];
     __shared__ uint32_t best[kCorrRows];
     __shared__ uint32_t rec_rd[4][kCap];
     __shared__ int32_t rec_col[4][kCap];
@@ -187,63 +196,103 @@ __global__ __launch_bounds__(256) void k_corr_search(CorrArgs a) {
     const int32_t *rows = a.free_idx + ca, *cols = a.free_idx + na;
     const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
     const int li = lane & 31, half = lane >> 5;
-    if (tid < kCorrRows) best[tid] = 0xffffffffu;
+    best[tid] = 0xffffffffu;
     if (tid < 12) geo[tid] = a.geo[12 * (size_t)q + tid];
-    __syncthreads();
 
     const v4i *pm = reinterpret_cast<const v4i *>(a.s.desc_pm);
     const v4i zero = {0, 0, 0, 0};
-    // A: this wavefront's 32 rows, lane holds row li, bytes [32t + 16 half, +16) for t < 8
-    v4i A[8];
-    {
-        const int r = row0 + wv * 32 + li;
+    // A: strip s of this wavefront, lane holds row li, bytes [32t + 16 half, +16) for t < 8
+    v4i A[kStrips][8];
+#pragma unroll
+    for (int s = 0; s < kStrips; ++s) {
+        const int r = row0 + 64 * wv + 32 * s + li;
         const v4i *src = pm + (size_t)(ca + (r < nr ? rows[r] : 0)) * 16 + half;
-        for (int t = 0; t < 8; ++t) A[t] = r < nr ? src[2 * t] : zero;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) A[s][t] = r < nr ? src[2 * t] : zero;
     }
+    // staging share of this thread: column tid / 8 of a tile, bytes [32 (tid % 8), +32)
+    const int scol = tid >> 3, spart = tid & 7;
+    v4i st0 = zero, st1 = zero;
+    auto load = [&](int tile) {
+        const int cc = tile * 32 + scol;
+        if (cc < nc) {
+            const v4i *src = pm + (size_t)(na + cols[cc]) * 16 + 2 * spart;
+            st0 = src[0];
+            st1 = src[1];
+        } else {
+            st0 = zero;
+            st1 = zero;
+        }
+    };
+    auto store = [&](int buf) {
+        v4i *dst = reinterpret_cast<v4i *>(tileB[buf] + scol * kColPad + 32 * spart);
+        dst[0] = st0;
+        dst[1] = st1;
+    };
+    const int ntiles = (nc + 31) / 32;
+    if (ntiles > 0) {
+        load(0);
+        store(0);
+    }
+    if (ntiles > 1) load(1);
+    __syncthreads();
+
     const int thr = 256 - 2 * a.th_low;
     int ncand = 0;
     uint32_t *my_rd = rec_rd[wv];
     int32_t *my_col = rec_col[wv];
     const uint64_t below = (1ull << lane) - 1ull;
-    const int ntiles = (nc + 31) / 32;
-    v4i B[8];
-    {
-        const int col = li;
-        const v4i *src = pm + (size_t)(na + (col < nc ? cols[col] : 0)) * 16 + half;
-        for (int t = 0; t < 8; ++t) B[t] = col < nc ? src[2 * t] : zero;
-    }
     for (int tile = 0; tile < ntiles; ++tile) {
-        v16i acc = {};
-        for (int t = 0; t < 8; ++t) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[t], B[t], acc, 0, 0, 0);
+        const int buf = tile & 1;
+        // buf ^ 1 was last read in the previous iteration, which ended at a barrier
+        if (tile + 1 < ntiles) store(buf ^ 1);
+        if (tile + 2 < ntiles) load(tile + 2);
+        v16i acc[kStrips];
+#pragma unroll
+        for (int s = 0; s < kStrips; ++s) acc[s] = v16i{};
+        const unsigned char *bt = tileB[buf] + li * kColPad + 16 * half;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const v4i b = *reinterpret_cast<const v4i *>(bt + 32 * t);
+#pragma unroll
+            for (int s = 0; s < kStrips; ++s)
+                acc[s] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[s][t], b, acc[s], 0, 0, 0);
+        }
         const int col = tile * 32 + li;
-        // next tile's operand, loaded while the products finish
-        if (tile + 1 < ntiles) {
-            const int cn = col + 32;
-            const v4i *src = pm + (size_t)(na + (cn < nc ? cols[cn] : 0)) * 16 + half;
-            for (int t = 0; t < 8; ++t) B[t] = cn < nc ? src[2 * t] : zero;
-        }
-        // output element v of lane l: row 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32
-        for (int v = 0; v < 16; ++v) {
-            const bool pass = acc[v] >= thr;
-            const uint64_t m = __ballot(pass);
-            if (m) {
-                if (pass) {
-                    const int pos = ncand + __popcll(m & below);
-                    const int rl = wv * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
-                    my_rd[pos] = ((uint32_t)rl << 16) | (uint32_t)((256 - acc[v]) >> 1);
-                    my_col[pos] = col;
+        // any candidate in this lane's 32 products?
+        int mx = acc[0][0];
+#pragma unroll
+        for (int s = 0; s < kStrips; ++s)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) mx = max(mx, acc[s][v]);
+        if (__ballot(mx >= thr)) {
+            // output element v of lane l: row 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32
+#pragma unroll
+            for (int s = 0; s < kStrips; ++s)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const bool pass = acc[s][v] >= thr;
+                    const uint64_t m = __ballot(pass);
+                    if (m) {
+                        if (pass) {
+                            const int pos = ncand + __popcll(m & below);
+                            const int rl = 64 * wv + 32 * s + 8 * (v >> 2) + 4 * half + (v & 3);
+                            my_rd[pos] = ((uint32_t)rl << 16) | (uint32_t)((256 - acc[s][v]) >> 1);
+                            my_col[pos] = col;
+                        }
+                        ncand += __popcll(m);
+                        if (ncand > kCap - 64) {
+                            corr_flush(a, geo, ca, na, rows, cols, row0, nr, nc, my_rd, my_col, ncand, best);
+                            ncand = 0;
+                        }
+                    }
                 }
-                ncand += __popcll(m);
-                if (ncand > kCap - 64) {
-                    corr_flush(a, geo, ca, na, rows, cols, row0, nr, nc, my_rd, my_col, ncand, best);
-                    ncand = 0;
-                }
-            }
         }
+        __syncthreads();
     }
     if (ncand > 0) corr_flush(a, geo, ca, na, rows, cols, row0, nr, nc, my_rd, my_col, ncand, best);
     __syncthreads();
-    if (tid < kCorrRows && row0 + tid < nr) {
+    if (row0 + tid < nr) {
         const uint32_t key = best[tid];
         if (key != 0xffffffffu) {
             const int il = rows[row0 + tid];

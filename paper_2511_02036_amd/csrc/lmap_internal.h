@@ -15,7 +15,7 @@ constexpr int kCell = LMAP_CELL_PX;
 constexpr int kDescBytes = 256;          // one descriptor as signed bytes
 constexpr int kKpBits = 22;              // resolution keys: distance << 22 | index
 constexpr uint32_t kKpMask = (1u << kKpBits) - 1u;
-constexpr int kCorrRows = 128;           // free keypoints of the current keyframe per block
+constexpr int kCorrRows = 256;           // free keypoints of the current keyframe per block
 
 // validation verdict words in the workspace (each a count of offending entries)
 enum {
