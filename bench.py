@@ -77,6 +77,18 @@ WORKLOADS = {
         desc="keyframe-culling counters over the observations of the 256-window batch (seed 4; 18M "
              "observations, 2.6M points, 5,700 keyframes, global indices, every 13th observation inactive)",
         precision="i32", z_f32=False, compare_plain=False),
+    "vi_stereo_fp64": dict(
+        desc="stereo-inertial local BA, seed 7: 10 optimisable + 5 fixed keyframes on a 4 m walk with "
+             "preintegrated IMU measurements between consecutive keyframes, 6,000 points, 8 observations per "
+             "point (70% stereo), 5% outliers; FP64, 15 unknowns per keyframe (joint reduced system of 150), "
+             "5+10 LM iterations",
+        precision="fp64", z_f32=False, compare_plain=False),
+    "vi_batched_mixed": dict(
+        desc="64 stereo-inertial windows (seed 8): keyframes U{6..15} with a third fixed (at most 12 "
+             "optimisable), points U{1,000..8,000}, 4-10 observations per point, 70/30 stereo/mono, IMU "
+             "measurements between consecutive keyframes; one batched solve per step, FP32 visual bulk + FP64 "
+             "inertial terms and reduced solve, 5+10 LM iterations",
+        precision="mixed", z_f32=True, compare_plain=False),
     "c3_precision_mixed": dict(
         desc="precision form, seed 2: 30 optimisable + 20 fixed stereo keyframes, 20,000 points, "
              "10 observations per point, FP32 bulk + FP64 reduced solve, 5+10 LM iterations",
@@ -514,6 +526,100 @@ def bench_map_search(args, spec):
     print(json.dumps(out), flush=True)
 
 
+def inertial_windows(name):
+    from paper_2511_02036_amd import synth
+    import numpy as np
+    if name == "vi_stereo_fp64":
+        return [synth.vi_stereo(seed=7)]
+    out = []
+    for i, ss in enumerate(np.random.SeedSequence(8).spawn(64)):
+        rng = np.random.default_rng(ss)
+        K = int(rng.integers(6, 16))
+        M = int(rng.integers(1000, 8001))
+        out.append(synth.vi_window(int(rng.integers(0, 2 ** 31)), K=K, n_fixed=max(K // 3, K - 12), M=M,
+                                   nobs=(4, 10), stereo_p=0.7, walk_length=0.3 * K))
+    return out
+
+
+def bench_inertial(args, spec):
+    """One step = one stereo-inertial solve (lba_solve_inertial) of the workload."""
+    import numpy as np
+    import torch
+    from paper_2511_02036_amd import lba, synth
+    pairs = inertial_windows(args.workload)
+    w, vi = pairs[0] if len(pairs) == 1 else synth.concat_vi(pairs)
+    dev = torch.device("cuda:0")
+    ctx = lba.Context(device=0, precision=spec["precision"])
+    prob = lba.DeviceProblem(w, device=dev, z_f32=spec["z_f32"])
+    dvi = lba.DeviceInertial(vi, device=dev)
+    solver = lba.InertialSolver(ctx, prob, dvi)
+    stream = torch.cuda.current_stream(dev)
+    for _ in range(max(args.warmup, 1)):
+        solver.run(stream)
+    torch.cuda.synchronize()
+    steps = max(args.steps, 1)
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        solver.run(stream)
+    torch.cuda.synchronize()
+    pel = time.perf_counter() - t0
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    solver.run(stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = 0
+    for _ in range(steps):
+        solver.run(stream)
+        iters += int(solver.stats[:, 2].sum() + solver.stats[:, 3].sum())
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    kern = {k: dict(launches=n, mean_us=1e3 * ms / n) for k, (n, ms) in prof.items() if n}
+    shapes = [window_shape(p[0]) for p in pairs]
+    mixed = spec["precision"] == "mixed"
+    r = kernel_roofs("linearize", shapes, kern["linearize"]["mean_us"], mixed, spec["z_f32"])
+    if r["alu_frac"] >= r["hbm_frac"]:
+        roof = dict(kernel="linearize", bound="alu", achieved=r["achieved_TFLOPs"], peak=r["alu_peak"],
+                    unit="TFLOP/s", frac=r["alu_frac"], traffic=None, mean_us=r["mean_us"],
+                    flops_per_launch=r["flops_per_launch"], hbm_frac=r["hbm_frac"])
+    else:
+        roof = dict(kernel="linearize", bound="hbm", achieved=r["achieved_GBs"], peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=r["hbm_frac"], traffic=None, mean_us=r["mean_us"], bytes_per_launch=r["bytes_per_launch"])
+    out = {"metric": METRIC, "value": iters / el, "unit": "window-LM-iterations/s", "n_gpus": 1, "steps": steps,
+           "warmup": args.warmup, "ms_per_step": 1e3 * el / steps, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32+f64" if mixed else "f64", "data": "synthetic",
+           "config": {"workload": args.workload, "description": spec["desc"], "windows": len(pairs),
+                      "keyframes": int(sum(s["K"] for s in shapes)), "points": int(sum(s["M"] for s in shapes)),
+                      "observations": int(sum(s["N"] for s in shapes)),
+                      "inertial_measurements": int(len(vi["dt"])),
+                      "lm_iterations_per_step": iters // steps},
+           "roofline": roof, "kernels_us_mean": {k: round(v["mean_us"], 2) for k, v in kern.items()},
+           "profiled": {"ms_per_step": 1e3 * pel / steps,
+                        "note": "the same steps with per-kernel HIP events, kernels launched one by one"}}
+    if not args.no_cpu_baseline:
+        from oracle import lbaref
+        zr = (lambda x: x)
+        if spec["z_f32"]:
+            from tests.parity import round_z_f32
+            zr = round_z_f32
+        t0 = time.perf_counter()
+        it = n = 0
+        res = {}
+        while n < len(pairs) and time.perf_counter() - t0 < 10.0:
+            rr = lbaref.solve_vi(zr(pairs[n][0]), pairs[n][1])
+            res[n] = rr
+            it += int(rr["stats"]["iters_r1"] + rr["stats"]["iters_r2"])
+            n += 1
+        cel = time.perf_counter() - t0
+        out["cpu_baseline"] = dict(value=it / cel, unit="window-LM-iterations/s", cores=1, kind="oracle",
+                                   sample=f"the first {n} of {len(pairs)} windows in {cel:.1f} s, one thread",
+                                   **host_description())
+        rel = [abs(solver.stats[i, 1] - rr["stats"]["F_final"]) / abs(rr["stats"]["F_final"]) for i, rr in res.items()]
+        out["parity"] = {"windows_checked": len(rel), "final_cost_rel_max": float(max(rel))}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -551,6 +657,9 @@ def main():
         return
     if args.workload in ("corr_search", "fusion_search", "culling_batched"):
         bench_map_search(args, spec)
+        return
+    if args.workload.startswith("vi_"):
+        bench_inertial(args, spec)
         return
     t_gen = time.perf_counter()
     windows = make_windows(args.workload)

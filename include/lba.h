@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define LBA_ABI_VERSION 2
+#define LBA_ABI_VERSION 3
 
 typedef enum {
     LBA_OK = 0,
@@ -55,9 +55,11 @@ typedef enum {
 
 typedef enum {
     LBA_PREC_FP64 = 0,   /* everything in FP64 */
-    LBA_PREC_MIXED = 1   /* Jacobians, Hessian blocks and Schur complement in FP32 with FP32
-                            accumulation; residuals, cost, gain ratio, damping, states and
-                            the reduced-camera-system Cholesky in FP64 */
+    LBA_PREC_MIXED = 1   /* Jacobians, Hessian blocks and the Schur products in FP32; the
+                            sums that form the Schur complement in FP64 (FP32 with
+                            schur_fp32_accum); residuals, cost, gain ratio, damping, states,
+                            the 3x3 point blocks and the reduced-camera-system Cholesky in
+                            FP64 */
 } lba_precision;
 
 /* Solver options.  lba_default_options() fills the values noted in brackets. */
@@ -82,6 +84,9 @@ typedef struct {
                                 by one while profiling is enabled [1] */
     int32_t trial_log;       /* records per window of the per-trial log kept in the workspace
                                 and returned through lba_result.log, 0..4096 [0] */
+    int32_t schur_fp32_accum; /* mixed precision only: 1 = sum the Schur complement and the
+                                 per-camera terms in FP32 (the literal precision form), 0 = in
+                                 FP64 from the FP32 products [0] */
 } lba_options;
 
 typedef struct {
@@ -192,25 +197,88 @@ lba_status lba_solve(lba_ctx *ctx, const lba_problem *problem, lba_result *resul
                      void *workspace, size_t workspace_bytes, void *stream);
 
 /* Solve many independent windows together: every kernel of an LM step covers all of
- * them in one launch, so windows of uneven size share the GPU.  Each window follows
- * exactly the schedule lba_solve gives it alone. */
+ * them in one launch, so windows of uneven size share the GPU.  Each window follows the
+ * schedule lba_solve gives it alone; the results agree to rounding (the linearisation
+ * sums its per-camera terms in no fixed order). */
 lba_status lba_solve_batch(lba_ctx *ctx, const lba_problem *problem, const lba_batch *batch,
                            lba_result *result, void *workspace, size_t workspace_bytes,
                            void *stream);
+
+/* ---- stereo-inertial form -------------------------------------------------------------
+ * The same solve with inertial residuals between keyframes (Section III-C: in visual-
+ * inertial systems the local bundle adjustment adds inertial residuals to the
+ * reprojection errors; the paper's runs are stereo-inertial, Section V-A).  Reading: the
+ * preintegrated IMU factor of Forster et al. (IEEE T-RO 2017) with a bias random walk.
+ *
+ *   states     per keyframe the pose T_cw and, in the world frame, the body velocity v,
+ *              gyroscope bias bg and accelerometer bias ba (fixed keyframes hold all);
+ *              the body pose is R = R_cw^T R_cb, p = R_cw^T (t_cb - t_cw) for the
+ *              body-to-camera transform T_cb = [R_cb | t_cb];
+ *   residual   of a measurement (dR, dv, dp over dt, integrated with biases bg_bar,
+ *              ba_bar, bias Jacobians J_Rg, J_vg, J_va, J_pg, J_pa) from keyframe i to j,
+ *              with dbg = bg_i - bg_bar and dba = ba_i - ba_bar:
+ *                r_R = Log((dR Exp(J_Rg dbg))^T R_i^T R_j)
+ *                r_v = R_i^T (v_j - v_i - g dt) - (dv + J_vg dbg + J_va dba)
+ *                r_p = R_i^T (p_j - p_i - v_i dt - g dt^2 / 2) - (dp + J_pg dbg + J_pa dba)
+ *                r_bg = bg_j - bg_i,  r_ba = ba_j - ba_i;
+ *   cost       r9^T info r9 + info_bg |r_bg|^2 + info_ba |r_ba|^2 (r9 = (r_R, r_v, r_p)),
+ *              added to the reprojection cost; no robust kernel;
+ *   step       15 unknowns per optimisable keyframe (twist, dv, dbg, dba), lambda on
+ *              every diagonal entry, the points eliminated as before; v, bg, ba move
+ *              additively.  The outlier pass and the schedule are those of lba_solve.
+ * The inertial terms are evaluated in FP64 in both precisions.  Limit: 15 Kopt <= 180
+ * (at most 12 optimisable keyframes per window). */
+typedef struct {
+    int32_t n_edges;          /* measurements over the batch */
+    int32_t reserved;
+    const int32_t *edge_off;  /* HOST n_windows + 1 (NULL for one window): window w owns the
+                                 measurements [edge_off[w], edge_off[w + 1]) */
+    const int32_t *edge_i;    /* DEVICE n_edges, window-local keyframe the measurement starts at */
+    const int32_t *edge_j;    /* DEVICE n_edges, window-local keyframe it ends at (!= edge_i) */
+    const double *dt;         /* DEVICE n_edges, seconds (> 0) */
+    const double *dR;         /* DEVICE n_edges x 9, row-major */
+    const double *dv, *dp;    /* DEVICE n_edges x 3 */
+    const double *J_Rg, *J_vg, *J_va, *J_pg, *J_pa;   /* DEVICE n_edges x 9 each, row-major */
+    const double *bg_bar, *ba_bar;                    /* DEVICE n_edges x 3 */
+    const double *info;       /* DEVICE n_edges x 81: information of (r_R, r_v, r_p), symmetric */
+    const double *info_bg, *info_ba;                  /* DEVICE n_edges */
+    const double *v, *bg, *ba;                        /* DEVICE n_kf x 3: initial states */
+    double T_cb[12];          /* body -> camera, row-major [R | t] */
+    double g[3];              /* gravity in the world frame */
+} lba_inertial;
+
+/* Bytes of DEVICE workspace lba_solve_inertial needs (batch NULL: one window). */
+lba_status lba_inertial_workspace_size(lba_ctx *ctx, const lba_problem *problem, const lba_batch *batch,
+                                       const lba_inertial *inertial, size_t *bytes);
+/* Solve one window or a batch with inertial measurements.  v_out, bg_out, ba_out: DEVICE
+ * n_kf x 3 each (may alias the inputs).  Everything else as lba_solve / lba_solve_batch;
+ * the costs in the statistics and the trial log include the inertial terms. */
+lba_status lba_solve_inertial(lba_ctx *ctx, const lba_problem *problem, const lba_batch *batch,
+                              const lba_inertial *inertial, lba_result *result, double *v_out, double *bg_out,
+                              double *ba_out, void *workspace, size_t workspace_bytes, void *stream);
 
 /* Tile tuner of the batched form.  The linearisation kernel runs one block per tile of
  * a window's points (the update one block per part of a tile); the tile size trades
  * per-tile work (the partial reduced system each tile writes and the fixed-order sum over
  * tiles) against the number of blocks that fill the GPU.  lba_tune times short solves
  * (three LM steps on every window, on `stream`; the least of three runs after a first
- * that captures the step graph) of this problem with candidate tile sizes 64 ... 4096 points, one
- * value per class of windows by optimisable keyframes (<= 10, <= 20, > 20), by coordinate
- * descent, and keeps the fastest table in the context: later solves of a problem with the
- * same sizes and precision use it when points_per_tile is 0.  The problem's inputs are
- * only read.  It allocates and frees its own device scratch (hipMalloc) and synchronises
- * the stream; points_per_tile (HOST, 3 entries, or NULL) receives the table. */
+ * that captures the step graph) of this problem with candidate tile sizes 64 ... 4096
+ * points, one value per class of windows (LBA_TUNE_CLASSES classes: optimisable
+ * keyframes <= 10, <= 20, > 20, times points < 2,000, < 8,000, >= 8,000; class index
+ * 3 * keyframe class + point class), by coordinate descent, and keeps the fastest table
+ * in the context: later solves of a problem with the same sizes and precision use it
+ * when points_per_tile is 0.  The problem's inputs are only read.  It allocates and frees
+ * its own device scratch (hipMalloc) and synchronises the stream; points_per_tile (HOST,
+ * LBA_TUNE_CLASSES entries, or NULL) receives the table.
+ * lba_tune_get copies the context's table (LBA_ERR_INVALID_ARGUMENT if it has none) so
+ * that a caller can store it; lba_tune_set installs a stored table (entries 1..65536), which
+ * then applies to every problem the context solves with points_per_tile 0 (NULL: forget
+ * it). */
+#define LBA_TUNE_CLASSES 9
 lba_status lba_tune(lba_ctx *ctx, const lba_problem *problem, const lba_batch *batch, void *stream,
                     int32_t *points_per_tile);
+lba_status lba_tune_get(const lba_ctx *ctx, int32_t *points_per_tile);
+lba_status lba_tune_set(lba_ctx *ctx, const int32_t *points_per_tile);
 
 /* ---- per-kernel timing ------------------------------------------------------------------
  * With profiling enabled, every kernel a solve launches is bracketed by two HIP events on
@@ -232,6 +300,7 @@ typedef enum {
     LBA_KCLASS_COST_FORWARD,     /* robust-cost layer, forward */
     LBA_KCLASS_COST_BACKWARD,    /* robust-cost layer, backward */
     LBA_KCLASS_ORDER,            /* once per solve: point order of the linearisation */
+    LBA_KCLASS_INERTIAL,         /* inertial measurements: residuals, blocks, joint system */
     LBA_KCLASS_COUNT
 } lba_kernel_class;
 

@@ -294,7 +294,7 @@ __device__ __forceinline__ unsigned block_inclusive_scan_total(unsigned v, int *
     return x + add;
 }
 
-template <typename Real, typename ZT>
+template <typename Real, typename ZT, typename Acc>
 __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
     using C = LinCfg<Real>;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -326,9 +326,9 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
     // upper positions 1 2 3 4 5 8 accumulate r of that camera, the rest are unused.
     const int grp = tid / 36, qe = tid - 36 * grp;
     const int nent = nblk;
-    double acc[kSlots];
+    Acc acc[kSlots];
 #pragma unroll
-    for (int k = 0; k < kSlots; ++k) acc[k] = 0.0;
+    for (int k = 0; k < kSlots; ++k) acc[k] = (Acc)0;
     unsigned long long m_r = 0, m_skip = 0;   // per slot: accumulates r / owns nothing
     {
         const int ie = qe / 6, je = qe - 6 * (qe / 6);
@@ -341,7 +341,9 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             else if (diag && rpos) m_r |= 1ull << k;
         }
     }
-    for (int i = tid; i < Kopt * 27; i += kNT) sm.dacc[i] = 0.0;
+    // per-camera self terms, in the accumulation type (the region is sized for FP64)
+    Acc *const dacc = reinterpret_cast<Acc *>(sm.dacc);
+    for (int i = tid; i < Kopt * 27; i += kNT) dacc[i] = (Acc)0;
     __syncthreads();
 
     const CamParams cam = a.c.cam;
@@ -507,18 +509,18 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             for (int i = 0; i < 18; ++i) sm.Z[tid * C::ZS + i] = Zr[i];
             // the observation's own term, D_a = Hpp_a - Z_a Z_a^T and r_a = bp_a - Z_a t, goes
             // straight into its camera's LDS sums
-            double *dst = sm.dacc + ka * 27;
+            Acc *dst = dacc + ka * 27;
             int e = 0;
 #pragma unroll
             for (int i = 0; i < 6; ++i)
 #pragma unroll
                 for (int j = 0; j <= i; ++j, ++e)
-                    lds_add(dst + e, (double)(H[i * 6 + j] - (Zr[i * 3] * Zr[j * 3] + Zr[i * 3 + 1] * Zr[j * 3 + 1] +
+                    lds_add(dst + e, (Acc)(H[i * 6 + j] - (Zr[i * 3] * Zr[j * 3] + Zr[i * 3 + 1] * Zr[j * 3 + 1] +
                                                               Zr[i * 3 + 2] * Zr[j * 3 + 2])));
 #pragma unroll
             for (int i = 0; i < 6; ++i)
                 lds_add(dst + 21 + i,
-                        bpd[i] - ((double)Zr[i * 3] * t0 + (double)Zr[i * 3 + 1] * t1 + (double)Zr[i * 3 + 2] * t2));
+                        (Acc)(bpd[i] - ((double)Zr[i * 3] * t0 + (double)Zr[i * 3 + 1] * t1 + (double)Zr[i * 3 + 2] * t2)));
         }
 
         // ---- 3. pair lists sorted by camera block --------------------------------------
@@ -672,9 +674,9 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
                 const int p0 = max(pco[B], b0) - b0, p1 = min(pco[B + 1], b0 + C::PB) - b0;
                 int pi = p0;   // four pieces per step: their loads are independent
                 for (; pi + 4 <= p1; pi += 4)
-                    acc[k] += ((double)col[pi * C::PS] + (double)col[(pi + 1) * C::PS]) +
-                              ((double)col[(pi + 2) * C::PS] + (double)col[(pi + 3) * C::PS]);
-                for (; pi < p1; ++pi) acc[k] += (double)col[pi * C::PS];
+                    acc[k] += ((Acc)col[pi * C::PS] + (Acc)col[(pi + 1) * C::PS]) +
+                              ((Acc)col[(pi + 2) * C::PS] + (Acc)col[(pi + 3) * C::PS]);
+                for (; pi < p1; ++pi) acc[k] += (Acc)col[pi * C::PS];
             }
             // the next batch overwrites the products; after the last one, the next chunk
             // writes this region only after its first barrier
@@ -694,15 +696,15 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             const int kA = block_row(B, Kopt);
             const int ri = qe <= 5 ? qe - 1 : 5;
             if ((m_r >> k) & 1) {
-                pr[6 * kA + ri] = sm.dacc[kA * 27 + 21 + ri];
+                pr[6 * kA + ri] = (double)dacc[kA * 27 + 21 + ri];
                 continue;
             }
             const int kB = kA + (B - block_id(kA, kA, Kopt));
             const int ie = qe / 6, je = qe - 6 * (qe / 6);
-            double v = acc[k];
-            if (kA == kB) v += sm.dacc[kA * 27 + ie * (ie + 1) / 2 + je];
+            Acc v = acc[k];
+            if (kA == kB) v += dacc[kA * 27 + ie * (ie + 1) / 2 + je];
             const int ra = 6 * kA + ie, col = 6 * kB + je;
-            part[ra >= col ? packed_lower(ra, col) : packed_lower(col, ra)] = v;
+            part[ra >= col ? packed_lower(ra, col) : packed_lower(col, ra)] = (double)v;
         }
     }
     Facc = wave_sum(Facc);
@@ -730,12 +732,15 @@ hipError_t launch_linearize(const LinArgs &a, int ntiles, size_t lds, bool mixed
     if (ntiles <= 0) return hipSuccess;
     dim3 grid(ntiles), block(kNT);
     const bool zf = a.obs.z_f32 != 0;
-    if (mixed) {
-        if (zf) hipLaunchKernelGGL((k_linearize<float, float>), grid, block, lds, s, a);
-        else hipLaunchKernelGGL((k_linearize<float, double>), grid, block, lds, s, a);
+    if (mixed && a.acc32) {   // the literal precision form: S summed in FP32
+        if (zf) hipLaunchKernelGGL((k_linearize<float, float, float>), grid, block, lds, s, a);
+        else hipLaunchKernelGGL((k_linearize<float, double, float>), grid, block, lds, s, a);
+    } else if (mixed) {
+        if (zf) hipLaunchKernelGGL((k_linearize<float, float, double>), grid, block, lds, s, a);
+        else hipLaunchKernelGGL((k_linearize<float, double, double>), grid, block, lds, s, a);
     } else {
-        if (zf) hipLaunchKernelGGL((k_linearize<double, float>), grid, block, lds, s, a);
-        else hipLaunchKernelGGL((k_linearize<double, double>), grid, block, lds, s, a);
+        if (zf) hipLaunchKernelGGL((k_linearize<double, float, double>), grid, block, lds, s, a);
+        else hipLaunchKernelGGL((k_linearize<double, double, double>), grid, block, lds, s, a);
     }
     return hipGetLastError();
 }

@@ -332,6 +332,8 @@ __global__ __launch_bounds__(64) void k_decide(DecideArgs a) {
         den += a.partu[4 * (u0 + t) + 1];
         fl = fmax(fl, a.partu[4 * (u0 + t) + 2]);
     }
+    if (a.vi_ed)   // the inertial measurements' costs at the trial state
+        for (int e = a.vi_edge_off[w] + lane; e < a.vi_edge_off[w + 1]; e += 64) Ft += a.vi_ed[(int64_t)e * kViEdgeStride + 1];
     Ft = wave_sum(Ft);
     den = wave_sum(den) + ctl->denom_p;
     fl = wave_max(fl);
@@ -390,6 +392,12 @@ __global__ __launch_bounds__(64) void k_decide(DecideArgs a) {
 #pragma unroll
             for (int i = 0; i < 12; ++i) Tin[i] = T[i];
             se3_left_update(dp + 6 * ok, Tin, T);
+            if (a.vi_state) {   // velocity and biases move additively
+                const double *d = a.vi_dp + a.vi_win[w].dp_off + 15 * ok + 6;
+                double *st = a.vi_state + 9 * (int64_t)(W.kf0 + k);
+#pragma unroll
+                for (int q = 0; q < 9; ++q) st[q] += d[q];
+            }
         }
     }
 }
@@ -437,16 +445,38 @@ __global__ __launch_bounds__(kInitRedThreads) void k_init_reduce(InitReduceArgs 
     for (int c = 0; c < kInitCols / 64; ++c) colsum[wave][lane + 64 * c] = cs[c];
     __syncthreads();
     double md = 0.0;
-    for (int i = tid; i < W.n; i += blockDim.x) {
-        double v = 0.0;
-        for (int g = 0; g < G; ++g) v += colsum[g][i];
-        md = fmax(md, v);
+    if (!a.vi_ed) {
+        for (int i = tid; i < W.n; i += blockDim.x) {
+            double v = 0.0;
+            for (int g = 0; g < G; ++g) v += colsum[g][i];
+            md = fmax(md, v);
+        }
+    } else {
+        // the joint diagonal: visual pose entries plus every inertial measurement's
+        // diagonal on the 15 unknowns of its two keyframes
+        const int e0 = a.vi_edge_off[w], e1 = a.vi_edge_off[w + 1];
+        for (int i = tid; i < 15 * W.Kopt; i += blockDim.x) {
+            const int o = i / 15, c = i % 15;
+            double v = 0.0;
+            if (c < 6)
+                for (int g = 0; g < G; ++g) v += colsum[g][6 * o + c];
+            for (int e = e0; e < e1; ++e) {
+                const double *rec = a.vi_ed + (int64_t)e * kViEdgeStride + kViH;
+                if (a.opt_map[W.kf0 + a.vi_ei[e]] == o) v += rec[c * (c + 1) / 2 + c];
+                if (a.opt_map[W.kf0 + a.vi_ej[e]] == o) v += rec[(15 + c) * (16 + c) / 2 + 15 + c];
+            }
+            md = fmax(md, v);
+        }
     }
     // ... and of the point blocks (per tile), and the cost
     double F = 0.0;
     for (int t = tid; t < W.ntiles; t += blockDim.x) md = fmax(md, a.partd[4 * (W.tile0 + t) + 1]);
-    if (wave == 0)
+    if (wave == 0) {
         for (int t = lane; t < W.ntiles; t += 64) F += a.partd[4 * (W.tile0 + t)];
+        if (a.vi_ed)
+            for (int e = a.vi_edge_off[w] + lane; e < a.vi_edge_off[w + 1]; e += 64)
+                F += a.vi_ed[(int64_t)e * kViEdgeStride];
+    }
     md = wave_max(md);
     F = wave_sum(F);
     if (lane == 0) smax[wave] = md;

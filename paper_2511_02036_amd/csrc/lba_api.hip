@@ -37,9 +37,11 @@ struct lba_ctx {
     };
     std::unordered_map<std::string, GraphEntry> graphs;
     uint64_t graph_clock = 0;
-    // tile tuner: points per tile by optimisable-keyframe class (Kopt <= 10, <= 20, > 20)
+    // tile tuner: points per tile by window class (optimisable keyframes x points, see
+    // window_class); tuned_sig[0] == -2 marks a table installed by lba_tune_set, which
+    // applies to every problem
     int64_t tuned_sig[5] = {-1, -1, -1, -1, -1};
-    int tuned_ppt[3] = {0, 0, 0};
+    int tuned_ppt[LBA_TUNE_CLASSES] = {};
     const int *ppt_override = nullptr;   // set while the tuner measures a candidate
     // kernel timing
     bool prof = false;
@@ -96,6 +98,11 @@ struct Plan {
     size_t o_ptstart, o_ctl, o_T, o_X0, o_X1, o_part, o_partr, o_partd, o_partu, o_red, o_redflag, o_dp, o_pf,
         o_pkey, o_ptmp, o_pinfo, o_skf, o_stype, o_soct, o_sz, o_smask, o_stats, o_err, o_log, total;
     int log_cap = 0;
+    // stereo-inertial solve
+    bool vi = false;
+    std::vector<WinInfo> vwin;         // joint reduced systems (n = 15 Kopt)
+    std::vector<int32_t> edge_win, edge_off;
+    size_t o_vwin = 0, o_edgewin = 0, o_edgeoff = 0, o_vred = 0, o_vdp = 0, o_state = 0, o_ed = 0;
 };
 
 int choose_points_per_tile(const lba_options &opt, int64_t total_points) {
@@ -123,6 +130,12 @@ int choose_cost_points_per_tile(const lba_options &opt, int64_t total_points, in
 
 int kopt_class(int kopt) { return kopt <= 10 ? 0 : (kopt <= 20 ? 1 : 2); }
 
+// tuner class of a window: optimisable keyframes (<= 10, <= 20, > 20) x points (< 2,000,
+// < 8,000, >= 8,000)
+int window_class(int kopt, int points) {
+    return 3 * kopt_class(kopt) + (points < 2000 ? 0 : (points < 8000 ? 1 : 2));
+}
+
 void tune_signature(const lba_problem *P, int nw, bool mixed, int64_t *sig) {
     sig[0] = P->n_kf;
     sig[1] = P->n_pt;
@@ -132,6 +145,7 @@ void tune_signature(const lba_problem *P, int nw, bool mixed, int64_t *sig) {
 }
 
 bool tune_signature_matches(const lba_ctx *ctx, const lba_problem *P, int nw, bool mixed) {
+    if (ctx->tuned_sig[0] == -2) return true;
     int64_t sig[5];
     tune_signature(P, nw, mixed, sig);
     for (int i = 0; i < 5; ++i)
@@ -139,7 +153,8 @@ bool tune_signature_matches(const lba_ctx *ctx, const lba_problem *P, int nw, bo
     return true;
 }
 
-lba_status build_plan(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, Plan &pl) {
+lba_status build_plan(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, Plan &pl,
+                      const lba_inertial *I = nullptr) {
     if (!P) return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "problem is NULL");
     if (P->n_kf < 0 || P->n_pt < 0 || P->n_obs < 0)
         return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "negative size");
@@ -212,10 +227,14 @@ lba_status build_plan(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, Pl
         if (kopt > kopt_max)
             return set_error(ctx, LBA_ERR_UNSUPPORTED, "window %d has %d optimisable keyframes (limit %d for this precision)",
                              w, kopt, kopt_max);
+        if (I && kopt > kMaxKoptInertial)
+            return set_error(ctx, LBA_ERR_UNSUPPORTED,
+                             "window %d has %d optimisable keyframes (limit %d with inertial measurements)", w, kopt,
+                             kMaxKoptInertial);
         W.Kopt = kopt;
         W.n = 6 * kopt;
         W.E = W.n * (W.n + 1) / 2;
-        const int ppt = class_ppt ? class_ppt[kopt_class(kopt)] : ppt_default;
+        const int ppt = class_ppt ? class_ppt[window_class(kopt, W.M)] : ppt_default;
         W.tile0 = (int)pl.tiles.size();
         W.ntiles = (W.M + ppt - 1) / ppt;
         for (int t = 0; t < W.ntiles; ++t) {
@@ -276,6 +295,43 @@ lba_status build_plan(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, Pl
     pl.lin_lds = lin_lds_bytes(maxK, maxn, 0, pl.mixed);
     pl.init_lds = init_lds_bytes(maxK, maxn);
     pl.upd_lds = upd_lds_bytes(maxK, maxn, pl.waves, pl.mixed);
+    // the inertial measurements: per window their range, the joint reduced system
+    pl.vi = I != nullptr;
+    int64_t vred = 0, vdp = 0;
+    if (pl.vi) {
+        if (I->n_edges < 0) return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "negative n_edges");
+        if (I->n_edges > 0 &&
+            (!I->edge_i || !I->edge_j || !I->dt || !I->dR || !I->dv || !I->dp || !I->J_Rg || !I->J_vg || !I->J_va ||
+             !I->J_pg || !I->J_pa || !I->bg_bar || !I->ba_bar || !I->info || !I->info_bg || !I->info_ba))
+            return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "an inertial measurement array is NULL");
+        if (P->n_kf > 0 && (!I->v || !I->bg || !I->ba))
+            return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "initial velocities / biases are NULL");
+        for (int q = 0; q < 12; ++q)
+            if (!std::isfinite(I->T_cb[q])) return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "T_cb not finite");
+        for (int q = 0; q < 3; ++q)
+            if (!std::isfinite(I->g[q])) return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "gravity not finite");
+        if (B && !I->edge_off) return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "edge_off is NULL for a batch");
+        if (B) pl.edge_off.assign(I->edge_off, I->edge_off + nw + 1);
+        else pl.edge_off = {0, I->n_edges};
+        if (pl.edge_off[0] != 0 || pl.edge_off[nw] != I->n_edges)
+            return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "edge offsets must start at 0 and end at n_edges");
+        pl.edge_win.assign(std::max(I->n_edges, 1), 0);
+        pl.vwin = pl.win;
+        for (int w = 0; w < nw; ++w) {
+            if (pl.edge_off[w + 1] < pl.edge_off[w])
+                return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "edge offsets decrease at window %d", w);
+            for (int e = pl.edge_off[w]; e < pl.edge_off[w + 1]; ++e) pl.edge_win[e] = w;
+            WinInfo &V = pl.vwin[w];
+            V.n = 15 * pl.win[w].Kopt;
+            V.E = V.n * (V.n + 1) / 2;
+            V.red_off = (int32_t)vred;
+            vred += V.E + V.n;
+            V.dp_off = (int32_t)vdp;
+            vdp += V.n;
+            maxn = std::max(maxn, V.n);
+        }
+        if (vred > INT32_MAX) return set_error(ctx, LBA_ERR_UNSUPPORTED, "batch too large");
+    }
     pl.chol_lds = chol_lds_bytes(maxn);
     if (pl.chol_lds > (size_t)ctx->max_lds)
         return set_error(ctx, LBA_ERR_UNSUPPORTED, "reduced system of %d unknowns does not fit in LDS", maxn);
@@ -289,6 +345,11 @@ lba_status build_plan(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, Pl
     pl.o_kfoff = o;  o = align256(o + sizeof(int32_t) * (nw + 1));
     pl.o_ptoff = o;  o = align256(o + sizeof(int32_t) * (nw + 1));
     pl.o_obsoff = o; o = align256(o + sizeof(int32_t) * (nw + 1));
+    if (pl.vi) {
+        pl.o_vwin = o;    o = align256(o + sizeof(WinInfo) * nw);
+        pl.o_edgewin = o; o = align256(o + sizeof(int32_t) * pl.edge_win.size());
+        pl.o_edgeoff = o; o = align256(o + sizeof(int32_t) * (nw + 1));
+    }
     pl.o_upload_end = o;
     pl.o_ptstart = o; o = align256(o + sizeof(int32_t) * ((size_t)P->n_pt + 1));
     pl.o_ctl = o;     o = align256(o + sizeof(Ctl) * nw);
@@ -326,6 +387,12 @@ lba_status build_plan(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, Pl
         return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "trial_log must be in [0, 4096]");
     pl.log_cap = opt.trial_log;
     pl.o_log = o;     o = align256(o + sizeof(TrialRec) * (size_t)pl.log_cap * nw);
+    if (pl.vi) {
+        pl.o_vred = o;  o = align256(o + sizeof(double) * std::max<int64_t>(vred, 1));
+        pl.o_vdp = o;   o = align256(o + sizeof(double) * std::max<int64_t>(vdp, 1));
+        pl.o_state = o; o = align256(o + sizeof(double) * 9 * std::max(P->n_kf, 1));
+        pl.o_ed = o;    o = align256(o + sizeof(double) * kViEdgeStride * std::max(I->n_edges, 1));
+    }
     pl.total = o;
     return LBA_OK;
 }
@@ -383,8 +450,10 @@ std::string describe_input_error(int32_t e) {
                            "octave >= n_levels", "observation type not 0/1",
                            "observations not grouped by point (obs_pt decreasing within a window)",
                            "non-finite measurement", "non-finite pose", "non-finite point",
-                           "a point has more than 64 observations", "stereo observation with bf <= 0"};
-    for (int b = 0; b < 10; ++b)
+                           "a point has more than 64 observations", "stereo observation with bf <= 0",
+                           "inertial measurement invalid (keyframe outside its window or repeated, dt <= 0, or a "
+                           "non-finite value) or non-finite initial velocity / bias"};
+    for (int b = 0; b < 11; ++b)
         if (e & (1 << b)) {
             if (!s.empty()) s += "; ";
             s += names[b];
@@ -471,13 +540,16 @@ lba_status step_graph(lba_ctx *ctx, const std::string &key, Fn &&step, hipGraphE
 }
 
 lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lba_result *R, void *ws,
-                      size_t ws_bytes, void *stream_ptr) {
+                      size_t ws_bytes, void *stream_ptr, const lba_inertial *I = nullptr, double *v_out = nullptr,
+                      double *bg_out = nullptr, double *ba_out = nullptr) {
     if (!ctx) return LBA_ERR_INVALID_ARGUMENT;
     ctx->err.clear();
     if (!R) return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "result is NULL");
     Plan pl;
-    lba_status st = build_plan(ctx, P, B, pl);
+    lba_status st = build_plan(ctx, P, B, pl, I);
     if (st != LBA_OK) return st;
+    if (I && P->n_kf > 0 && (!v_out || !bg_out || !ba_out))
+        return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "v_out / bg_out / ba_out is NULL");
     if (P->n_kf > 0 && !R->T_out) return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "T_out is NULL");
     if (P->n_pt > 0 && !R->X_out) return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "X_out is NULL");
     if (P->n_obs > 0 && !R->outlier) return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "outlier is NULL");
@@ -510,6 +582,11 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
     memcpy(up + pl.o_kfoff, pl.kf_off.data(), sizeof(int32_t) * (nw + 1));
     memcpy(up + pl.o_ptoff, pl.pt_off.data(), sizeof(int32_t) * (nw + 1));
     memcpy(up + pl.o_obsoff, pl.obs_off.data(), sizeof(int32_t) * (nw + 1));
+    if (pl.vi) {
+        memcpy(up + pl.o_vwin, pl.vwin.data(), sizeof(WinInfo) * nw);
+        memcpy(up + pl.o_edgewin, pl.edge_win.data(), sizeof(int32_t) * pl.edge_win.size());
+        memcpy(up + pl.o_edgeoff, pl.edge_off.data(), sizeof(int32_t) * (nw + 1));
+    }
     HIPCHK(hipMemcpyAsync(wsb, up, pl.o_upload_end, hipMemcpyHostToDevice, s));
     st = record_upload(ctx, s);
     if (st != LBA_OK) return st;
@@ -579,8 +656,46 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
     m.n_levels = P->n_levels;
     m.c = c;
 
+    // the inertial measurements (stereo-inertial solve)
+    ViArgs va;
+    memset(&va, 0, sizeof(va));
+    if (pl.vi) {
+        va.E = {I->edge_i, I->edge_j, I->dt, I->dR, I->dv, I->dp, I->J_Rg, I->J_vg, I->J_va, I->J_pg, I->J_pa,
+                I->bg_bar, I->ba_bar, I->info, I->info_bg, I->info_ba, I->n_edges, 0};
+        va.win = d_win;
+        va.vwin = static_cast<const WinInfo *>(W_(pl.o_vwin));
+        va.edge_win = static_cast<const int32_t *>(W_(pl.o_edgewin));
+        va.edge_off = static_cast<const int32_t *>(W_(pl.o_edgeoff));
+        va.opt_map = static_cast<const int32_t *>(W_(pl.o_opt));
+        va.ctl = d_ctl;
+        va.T = d_T;
+        va.state = static_cast<double *>(W_(pl.o_state));
+        va.v0 = I->v;
+        va.bg0 = I->bg;
+        va.ba0 = I->ba;
+        va.v_out = v_out;
+        va.bg_out = bg_out;
+        va.ba_out = ba_out;
+        va.dp = d_dp;
+        va.dpv = d_dp;
+        va.vdp = static_cast<double *>(W_(pl.o_vdp));
+        va.red = d_red;
+        va.vred = static_cast<double *>(W_(pl.o_vred));
+        va.ed = static_cast<double *>(W_(pl.o_ed));
+        va.err = d_err;
+        for (int q = 0; q < 12; ++q) va.Tcb[q] = I->T_cb[q];
+        for (int q = 0; q < 3; ++q) va.g[q] = I->g[q];
+        va.n_kf = P->n_kf;
+    }
+    ViArgs va_trial = va;
+    va_trial.trial = 1;
+
     HIPCHK(timed(ctx, LBA_KCLASS_SETUP, s, [&] { return launch_setup(m, nw, s); }));
     HIPCHK(timed(ctx, LBA_KCLASS_VALIDATE, s, [&] { return launch_validate(m, nw, pl.max_obs, s); }));
+    if (pl.vi) {
+        HIPCHK(timed(ctx, LBA_KCLASS_VALIDATE, s, [&] { return launch_vi_check(va, s); }));
+        HIPCHK(timed(ctx, LBA_KCLASS_SETUP, s, [&] { return launch_vi_setup(va, s); }));
+    }
     HIPCHK(hipMemcpyAsync(down, d_err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     int32_t in_err;
@@ -641,6 +756,7 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
     la.partd = d_partd;
     la.pf = static_cast<double *>(W_(pl.o_pf));
     la.waves = pl.waves;
+    la.acc32 = (pl.mixed && opt.schur_fp32_accum) ? 1 : 0;
     la.c = c;
 
     ReduceArgs ra;
@@ -661,6 +777,11 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
     ca.red = d_red;
     ca.redflag = d_redflag;
     ca.dp = d_dp;
+    if (pl.vi) {   // the joint reduced system of 15 Kopt unknowns per window
+        ca.win = va.vwin;
+        ca.red = va.vred;
+        ca.dp = static_cast<double *>(W_(pl.o_vdp));
+    }
 
     UpdArgs ua;
     memset(&ua, 0, sizeof(ua));
@@ -693,6 +814,13 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
     da.log_cap = pl.log_cap;
     da.split = pl.upd_split;
     da.c = c;
+    if (pl.vi) {
+        da.vi_ed = va.ed;
+        da.vi_edge_off = va.edge_off;
+        da.vi_dp = va.vdp;
+        da.vi_win = va.vwin;
+        da.vi_state = va.state;
+    }
 
     InitReduceArgs ia;
     memset(&ia, 0, sizeof(ia));
@@ -701,6 +829,13 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
     ia.partr = static_cast<const double *>(W_(pl.o_partr));
     ia.partd = d_partd;
     ia.c = c;
+    if (pl.vi) {
+        ia.vi_ed = va.ed;
+        ia.vi_edge_off = va.edge_off;
+        ia.vi_ei = I->edge_i;
+        ia.vi_ej = I->edge_j;
+        ia.opt_map = va.opt_map;
+    }
 
     std::vector<Ctl> hctl(nw);
     for (int round = 1; round <= 2; ++round) {
@@ -724,6 +859,7 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
         da.round = round;
         ia.round = round;
         HIPCHK(timed(ctx, LBA_KCLASS_LINEARIZE_INIT, s, [&] { return launch_init(la, ntiles, pl.init_lds, s); }));
+        if (pl.vi) HIPCHK(timed(ctx, LBA_KCLASS_INERTIAL, s, [&] { return launch_vi_eval(va, s); }));
         HIPCHK(timed(ctx, LBA_KCLASS_INIT_REDUCE, s, [&] { return launch_init_reduce(ia, nw, s); }));
         int steps_done = 0;
         int nsteps = iters;
@@ -735,11 +871,21 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
                            [&] { return launch_linearize(la, ntiles, pl.lin_lds, pl.mixed, q); })) != hipSuccess)
                 return e;
             if ((e = timed(ctx, LBA_KCLASS_REDUCE, q, [&] { return launch_reduce(ra, nw, q); })) != hipSuccess) return e;
+            if (pl.vi) {
+                if ((e = timed(ctx, LBA_KCLASS_INERTIAL, q, [&] { return launch_vi_eval(va, q); })) != hipSuccess) return e;
+                if ((e = timed(ctx, LBA_KCLASS_INERTIAL, q, [&] { return launch_vi_system(va, nw, q); })) != hipSuccess)
+                    return e;
+            }
             if ((e = timed(ctx, LBA_KCLASS_CHOLESKY, q, [&] { return launch_cholesky(ca, nw, pl.chol_lds, q); })) !=
                 hipSuccess)
                 return e;
+            if (pl.vi && (e = timed(ctx, LBA_KCLASS_INERTIAL, q, [&] { return launch_vi_split(va, nw, q); })) != hipSuccess)
+                return e;
             if ((e = timed(ctx, LBA_KCLASS_UPDATE, q,
                            [&] { return launch_update(ua, ntiles, pl.upd_lds, pl.mixed, q); })) != hipSuccess)
+                return e;
+            if (pl.vi && (e = timed(ctx, LBA_KCLASS_INERTIAL, q, [&] { return launch_vi_eval(va_trial, q); })) !=
+                             hipSuccess)
                 return e;
             return timed(ctx, LBA_KCLASS_DECIDE, q, [&] { return launch_decide(da, nw, q); });
         };
@@ -752,6 +898,7 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
             add(&ca, sizeof(ca));
             add(&ua, sizeof(ua));
             add(&da, sizeof(da));
+            add(&va, sizeof(va));
             const int64_t dims[6] = {ntiles, nw, (int64_t)pl.lin_lds, (int64_t)pl.chol_lds, (int64_t)pl.upd_lds,
                                      pl.mixed ? 1 : 0};
             add(dims, sizeof(dims));
@@ -776,6 +923,7 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
     m.count = 1;
     HIPCHK(timed(ctx, LBA_KCLASS_FLAGS, s, [&] { return launch_flags(m, nw, pl.max_obs, s); }));
     HIPCHK(timed(ctx, LBA_KCLASS_FINALIZE, s, [&] { return launch_finalize(m, nw, s); }));
+    if (pl.vi) HIPCHK(timed(ctx, LBA_KCLASS_FINALIZE, s, [&] { return launch_vi_finish(va, s); }));
     if (R->log && pl.log_cap > 0)
         HIPCHK(hipMemcpyAsync(R->log, W_(pl.o_log), sizeof(TrialRec) * (size_t)pl.log_cap * nw,
                               hipMemcpyDeviceToHost, s));
@@ -1153,21 +1301,15 @@ lba_status lba_tune(lba_ctx *ctx, const lba_problem *problem, const lba_batch *b
     Plan pl0;
     lba_status st = build_plan(ctx, problem, batch, pl0);
     if (st != LBA_OK) return st;
-    bool present[3] = {false, false, false};
-    for (const WinInfo &W : pl0.win) present[kopt_class(W.Kopt)] = true;
-    // the smallest tiles give the most tiles, hence the largest workspace of any candidate
+    bool present[LBA_TUNE_CLASSES] = {};
+    for (const WinInfo &W : pl0.win) present[window_class(W.Kopt, W.M)] = true;
     static const int cand[] = {64, 128, 256, 512, 1024, 2048, 4096};
-    const int smallest[3] = {cand[0], cand[0], cand[0]};
-    ctx->ppt_override = smallest;
-    Plan pmax;
-    st = build_plan(ctx, problem, batch, pmax);
-    ctx->ppt_override = nullptr;
-    if (st != LBA_OK) return st;
 
     DeviceGuard dg;
     HIPCHK(dg.enter(ctx->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     void *ws = nullptr, *T = nullptr, *X = nullptr, *fl = nullptr;
+    size_t ws_bytes = 0;
     auto release = [&] {
         (void)hipStreamSynchronize(s);
         for (auto &g : ctx->graphs) {
@@ -1180,12 +1322,11 @@ lba_status lba_tune(lba_ctx *ctx, const lba_problem *problem, const lba_batch *b
         if (X) (void)hipFree(X);
         if (fl) (void)hipFree(fl);
     };
-    if (hipMalloc(&ws, pmax.total) != hipSuccess ||
-        hipMalloc(&T, sizeof(double) * 12 * std::max(problem->n_kf, 1)) != hipSuccess ||
+    if (hipMalloc(&T, sizeof(double) * 12 * std::max(problem->n_kf, 1)) != hipSuccess ||
         hipMalloc(&X, sizeof(double) * 3 * std::max(problem->n_pt, 1)) != hipSuccess ||
         hipMalloc(&fl, std::max(problem->n_obs, 1)) != hipSuccess) {
         release();
-        return set_error(ctx, LBA_ERR_HIP, "lba_tune: device allocation of %zu bytes failed", pmax.total);
+        return set_error(ctx, LBA_ERR_HIP, "lba_tune: device allocation failed");
     }
     const lba_options saved = ctx->opt;
     const bool saved_prof = ctx->prof;
@@ -1195,17 +1336,35 @@ lba_status lba_tune(lba_ctx *ctx, const lba_problem *problem, const lba_batch *b
     ctx->prof = false;
     lba_result R = {static_cast<double *>(T), static_cast<double *>(X), static_cast<uint8_t *>(fl), nullptr,
                     nullptr};
-    int cfg[3];
+    int cfg[LBA_TUNE_CLASSES];
     double best = 0.0;
-    // time of one short solve (three LM steps on every window) with the tile table cfg:
-    // the first run captures the step graph, the least of the next three is taken
+    // time of one short solve (three LM steps on every window) with the tile table c: the
+    // workspace grows to the candidate's plan when it needs more (a table's size depends
+    // on its tiles and on the update's parts per tile); the first run captures the step
+    // graph, the least of the next three is taken
     auto measure = [&](const int *c, double *sec) -> lba_status {
         ctx->ppt_override = c;
+        Plan pc;
+        lba_status e = build_plan(ctx, problem, batch, pc);
+        if (e != LBA_OK) return e;
+        if (pc.total > ws_bytes) {
+            if (hipStreamSynchronize(s) != hipSuccess) return set_error(ctx, LBA_ERR_HIP, "stream sync failed");
+            for (auto &g : ctx->graphs) {   // captured graphs hold the old workspace's address
+                (void)hipGraphExecDestroy(g.second.exec);
+                (void)hipGraphDestroy(g.second.graph);
+            }
+            ctx->graphs.clear();
+            if (ws) (void)hipFree(ws);
+            ws = nullptr;
+            if (hipMalloc(&ws, pc.total) != hipSuccess)
+                return set_error(ctx, LBA_ERR_HIP, "lba_tune: device allocation of %zu bytes failed", pc.total);
+            ws_bytes = pc.total;
+        }
         *sec = 0.0;
         for (int rep = 0; rep < 4; ++rep) {
             if (hipStreamSynchronize(s) != hipSuccess) return set_error(ctx, LBA_ERR_HIP, "stream sync failed");
             const auto t0 = std::chrono::steady_clock::now();
-            lba_status e = solve_impl(ctx, problem, batch, &R, ws, pmax.total, stream);
+            e = solve_impl(ctx, problem, batch, &R, ws, ws_bytes, stream);
             if (e != LBA_OK) return e;
             if (hipStreamSynchronize(s) != hipSuccess) return set_error(ctx, LBA_ERR_HIP, "stream sync failed");
             const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -1214,14 +1373,15 @@ lba_status lba_tune(lba_ctx *ctx, const lba_problem *problem, const lba_batch *b
         return LBA_OK;
     };
     const int start = choose_points_per_tile(saved, problem->n_pt);
-    for (int c = 0; c < 3; ++c) cfg[c] = start;
+    for (int c = 0; c < LBA_TUNE_CLASSES; ++c) cfg[c] = start;
     st = measure(cfg, &best);
     // coordinate descent over the classes present; a change must gain 1%
-    for (int c = 0; c < 3 && st == LBA_OK; ++c) {
+    for (int c = 0; c < LBA_TUNE_CLASSES && st == LBA_OK; ++c) {
         if (!present[c]) continue;
         for (int v : cand) {
             if (v == cfg[c]) continue;
-            int trial[3] = {cfg[0], cfg[1], cfg[2]};
+            int trial[LBA_TUNE_CLASSES];
+            for (int q = 0; q < LBA_TUNE_CLASSES; ++q) trial[q] = cfg[q];
             trial[c] = v;
             double t = 0.0;
             st = measure(trial, &t);
@@ -1238,10 +1398,53 @@ lba_status lba_tune(lba_ctx *ctx, const lba_problem *problem, const lba_batch *b
     release();
     if (st != LBA_OK) return st;
     tune_signature(problem, pl0.nw, pl0.mixed, ctx->tuned_sig);
-    for (int c = 0; c < 3; ++c) ctx->tuned_ppt[c] = cfg[c];
+    for (int c = 0; c < LBA_TUNE_CLASSES; ++c) ctx->tuned_ppt[c] = cfg[c];
     if (points_per_tile)
-        for (int c = 0; c < 3; ++c) points_per_tile[c] = cfg[c];
+        for (int c = 0; c < LBA_TUNE_CLASSES; ++c) points_per_tile[c] = cfg[c];
     return LBA_OK;
+}
+
+lba_status lba_tune_get(const lba_ctx *ctx, int32_t *points_per_tile) {
+    if (!ctx || !points_per_tile) return LBA_ERR_INVALID_ARGUMENT;
+    if (ctx->tuned_sig[0] == -1) return LBA_ERR_INVALID_ARGUMENT;
+    for (int c = 0; c < LBA_TUNE_CLASSES; ++c) points_per_tile[c] = ctx->tuned_ppt[c];
+    return LBA_OK;
+}
+
+lba_status lba_tune_set(lba_ctx *ctx, const int32_t *points_per_tile) {
+    if (!ctx) return LBA_ERR_INVALID_ARGUMENT;
+    ctx->err.clear();
+    if (!points_per_tile) {   // forget the table
+        ctx->tuned_sig[0] = -1;
+        return LBA_OK;
+    }
+    for (int c = 0; c < LBA_TUNE_CLASSES; ++c)
+        if (points_per_tile[c] < 1 || points_per_tile[c] > 65536)
+            return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "points per tile of class %d must be in [1, 65536]", c);
+    for (int c = 0; c < LBA_TUNE_CLASSES; ++c) ctx->tuned_ppt[c] = points_per_tile[c];
+    ctx->tuned_sig[0] = -2;
+    return LBA_OK;
+}
+
+lba_status lba_inertial_workspace_size(lba_ctx *ctx, const lba_problem *problem, const lba_batch *batch,
+                                       const lba_inertial *inertial, size_t *bytes) {
+    if (!ctx) return LBA_ERR_INVALID_ARGUMENT;
+    ctx->err.clear();
+    if (!bytes || !inertial) return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "bytes / inertial is NULL");
+    Plan pl;
+    lba_status st = build_plan(ctx, problem, batch, pl, inertial);
+    if (st != LBA_OK) return st;
+    *bytes = pl.total;
+    return LBA_OK;
+}
+
+lba_status lba_solve_inertial(lba_ctx *ctx, const lba_problem *problem, const lba_batch *batch,
+                              const lba_inertial *inertial, lba_result *result, double *v_out, double *bg_out,
+                              double *ba_out, void *workspace, size_t workspace_bytes, void *stream) {
+    if (!ctx) return LBA_ERR_INVALID_ARGUMENT;
+    if (!inertial) return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "inertial is NULL");
+    return solve_impl(ctx, problem, batch, result, workspace, workspace_bytes, stream, inertial, v_out, bg_out,
+                      ba_out);
 }
 
 lba_status lba_solve_batch(lba_ctx *ctx, const lba_problem *problem, const lba_batch *batch, lba_result *result,

@@ -100,6 +100,8 @@ struct LinArgs {
     double *pf;                  // per point: L^-1 of V (6), t = L^-1 bl (3), bl (3)
     int robust;
     int waves;
+    int acc32;                   // mixed precision: sum S and the self terms in FP32
+    int pad;
     SolveConsts c;
 };
 
@@ -124,6 +126,17 @@ struct OrderArgs {
     const uint8_t *mask;         // k_order_gather_mask: outlier flags in index order ...
     uint8_t *smask;              // ... and in places
 };
+
+// stereo-inertial measurements (device view of lba_inertial)
+struct ViEdges {
+    const int32_t *ei, *ej;
+    const double *dt, *dR, *dv, *dp, *JRg, *Jvg, *Jva, *Jpg, *Jpa, *bgb, *bab, *info, *ibg, *iba;
+    int32_t n, pad;
+};
+
+constexpr int kViEdgeStride = 512;   // doubles per measurement: cost, trial cost, b (30), H (465)
+constexpr int kViB = 2, kViH = 32;   // offsets of b and of the packed lower H in a record
+constexpr int kMaxKoptInertial = 12; // 15 Kopt <= 180
 
 struct ReduceArgs {
     const WinInfo *win;
@@ -176,6 +189,12 @@ struct DecideArgs {
     int split;
     int round;                   // 1 or 2
     SolveConsts c;
+    // stereo-inertial solve (null otherwise)
+    const double *vi_ed;         // measurement records: trial costs
+    const int32_t *vi_edge_off;
+    const double *vi_dp;         // joint step
+    const WinInfo *vi_win;
+    double *vi_state;
 };
 
 struct InitReduceArgs {
@@ -185,6 +204,12 @@ struct InitReduceArgs {
     const double *partd;
     int round;
     SolveConsts c;
+    // stereo-inertial solve (null otherwise): measurement records, their windows and
+    // keyframes
+    const double *vi_ed;
+    const int32_t *vi_edge_off;
+    const int32_t *vi_ei, *vi_ej;
+    const int32_t *opt_map;
 };
 
 struct MiscArgs {
@@ -245,6 +270,38 @@ struct CostArgs {
 // ------------------------------------------------------------------------------------
 // launchers (one per translation unit that owns the kernel)
 // ------------------------------------------------------------------------------------
+struct ViArgs {
+    ViEdges E;
+    const WinInfo *win;          // visual records
+    const WinInfo *vwin;         // records of the joint reduced system: n = 15 Kopt, E, red_off, dp_off
+    const int32_t *edge_win;     // window of each measurement
+    const int32_t *edge_off;     // n_windows + 1
+    const int32_t *opt_map;
+    Ctl *ctl;
+    const double *T;             // current poses
+    double *state;               // per keyframe: v (3), bg (3), ba (3)
+    const double *v0, *bg0, *ba0;
+    double *v_out, *bg_out, *ba_out;
+    const double *dp;            // visual pose step (6 per optimisable keyframe)
+    double *dpv;                 // visual pose step written from the joint one
+    const double *vdp;           // joint step (15 per optimisable keyframe)
+    const double *red;           // visual reduced system (packed lower S, then r)
+    double *vred;                // joint reduced system
+    double *ed;                  // per measurement record (kViEdgeStride doubles)
+    int32_t *err;
+    double Tcb[12];
+    double g[3];
+    int trial;                   // k_vi_eval: 0 = linearise at the current state, 1 = trial cost
+    int n_kf;
+};
+
+hipError_t launch_vi_setup(const ViArgs &a, hipStream_t s);
+hipError_t launch_vi_check(const ViArgs &a, hipStream_t s);
+hipError_t launch_vi_eval(const ViArgs &a, hipStream_t s);
+hipError_t launch_vi_system(const ViArgs &a, int n_windows, hipStream_t s);
+hipError_t launch_vi_split(const ViArgs &a, int n_windows, hipStream_t s);
+hipError_t launch_vi_finish(const ViArgs &a, hipStream_t s);
+
 hipError_t launch_linearize(const LinArgs &a, int ntiles, size_t lds, bool mixed, hipStream_t s);
 hipError_t launch_update(const UpdArgs &a, int ntiles, size_t lds, bool mixed, hipStream_t s);
 hipError_t launch_init(const LinArgs &a, int ntiles, size_t lds, hipStream_t s);

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "liblba.so")
 PREC_FP64 = 0
 PREC_MIXED = 1
 STATS_LEN = 12
+TUNE_CLASSES = 9
 STAT_NAMES = ["F_initial", "F_final", "iters_r1", "iters_r2", "trials", "lambda", "term_r1",
               "term_r2", "n_outliers", "F_end_r1", "F_start_r2", "Kopt"]
 
@@ -28,11 +29,12 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "out of memory", -3: "HIP runtime
 EXPORTS = ["lba_abi_version", "lba_status_string", "lba_default_options", "lba_create",
            "lba_destroy", "lba_last_error", "lba_set_options", "lba_workspace_size", "lba_solve",
            "lba_solve_batch", "lba_profile_enable", "lba_profile_read", "lba_cost_workspace_size",
-           "lba_cost_forward", "lba_cost_backward", "lba_tune"]
+           "lba_cost_forward", "lba_cost_backward", "lba_tune", "lba_inertial_workspace_size",
+           "lba_solve_inertial", "lba_tune_get", "lba_tune_set"]
 
 KERNEL_CLASSES = ["linearize", "linearize_init", "reduce", "cholesky", "update", "decide",
                   "init_reduce", "setup", "validate", "flags", "finalize", "cost_forward",
-                  "cost_backward", "order"]
+                  "cost_backward", "order", "inertial"]
 
 
 class Options(C.Structure):
@@ -40,7 +42,8 @@ class Options(C.Structure):
                 ("max_trials", C.c_int32), ("round2_robust", C.c_int32), ("check_inputs", C.c_int32),
                 ("huber2_mono", C.c_double), ("huber2_stereo", C.c_double),
                 ("chi2_mono", C.c_double), ("chi2_stereo", C.c_double), ("tau", C.c_double),
-                ("points_per_tile", C.c_int32), ("use_graphs", C.c_int32), ("trial_log", C.c_int32)]
+                ("points_per_tile", C.c_int32), ("use_graphs", C.c_int32), ("trial_log", C.c_int32),
+                ("schur_fp32_accum", C.c_int32)]
 
 
 class Intrinsics(C.Structure):
@@ -66,6 +69,15 @@ class TrialRecord(C.Structure):
     _fields_ = [("round", C.c_int32), ("iter", C.c_int32), ("trial", C.c_int32),
                 ("accepted", C.c_int32), ("solve_ok", C.c_int32), ("reserved", C.c_int32),
                 ("lam", C.c_double), ("F", C.c_double), ("F_trial", C.c_double), ("gain", C.c_double)]
+
+
+VI_ARRAYS = ["edge_i", "edge_j", "dt", "dR", "dv", "dp", "J_Rg", "J_vg", "J_va", "J_pg", "J_pa", "bg_bar",
+             "ba_bar", "info", "info_bg", "info_ba", "v", "bg", "ba"]
+
+
+class Inertial(C.Structure):
+    _fields_ = [("n_edges", C.c_int32), ("reserved", C.c_int32), ("edge_off", C.c_void_p)] + \
+        [(k, C.c_void_p) for k in VI_ARRAYS] + [("T_cb", C.c_double * 12), ("g", C.c_double * 3)]
 
 
 class Result(C.Structure):
@@ -122,6 +134,17 @@ def library():
         L.lba_tune.argtypes = [C.c_void_p, C.POINTER(Problem), C.POINTER(Batch), C.c_void_p,
                                C.POINTER(C.c_int32)]
         L.lba_tune.restype = C.c_int
+        L.lba_tune_get.argtypes = [C.c_void_p, C.POINTER(C.c_int32)]
+        L.lba_tune_get.restype = C.c_int
+        L.lba_tune_set.argtypes = [C.c_void_p, C.POINTER(C.c_int32)]
+        L.lba_tune_set.restype = C.c_int
+        L.lba_inertial_workspace_size.argtypes = [C.c_void_p, C.POINTER(Problem), C.POINTER(Batch),
+                                                  C.POINTER(Inertial), C.POINTER(C.c_size_t)]
+        L.lba_inertial_workspace_size.restype = C.c_int
+        L.lba_solve_inertial.argtypes = [C.c_void_p, C.POINTER(Problem), C.POINTER(Batch), C.POINTER(Inertial),
+                                         C.POINTER(Result), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                         C.c_size_t, C.c_void_p]
+        L.lba_solve_inertial.restype = C.c_int
         _lib = L
     return _lib
 
@@ -179,13 +202,24 @@ class Context:
 
     def tune(self, prob: "DeviceProblem", stream=None) -> list:
         """Run the tile tuner on this problem (see lba_tune); returns the points-per-tile
-        table by optimisable-keyframe class (<= 10, <= 20, > 20)."""
+        table by window class (TUNE_CLASSES entries: 3 * keyframe class + point class)."""
         import torch
         stream = stream or torch.cuda.current_stream(prob.device)
-        out = (C.c_int32 * 3)()
+        out = (C.c_int32 * TUNE_CLASSES)()
         self._check(self.lib.lba_tune(self.handle, C.byref(prob.problem), C.byref(prob.batch),
                                       C.c_void_p(stream.cuda_stream), out), "lba_tune")
         return list(out)
+
+    def tune_table(self) -> list:
+        """The context's tile table (lba_tune_get), to be stored by the caller."""
+        out = (C.c_int32 * TUNE_CLASSES)()
+        self._check(self.lib.lba_tune_get(self.handle, out), "lba_tune_get")
+        return list(out)
+
+    def set_tune_table(self, table) -> None:
+        """Install a stored tile table (lba_tune_set); None forgets it."""
+        arr = None if table is None else (C.c_int32 * TUNE_CLASSES)(*[int(x) for x in table])
+        self._check(self.lib.lba_tune_set(self.handle, arr), "lba_tune_set")
 
     def close(self):
         if getattr(self, "handle", None):
@@ -290,6 +324,88 @@ class Solver:
                              solve_ok=bool(r.solve_ok), lam=r.lam, F=r.F, F_trial=r.F_trial, gain=r.gain)
                         for r in recs])
         return out
+
+
+class DeviceInertial:
+    """The inertial measurements and initial velocities / biases of a window or a batch on
+    the GPU.  ``vi`` is a dict of arrays as ``synth.vi_window`` returns (concatenated over
+    windows with ``edge_off`` for a batch: window-local keyframe indices)."""
+
+    def __init__(self, vi: dict, device="cuda"):
+        import torch
+        dev = torch.device(device)
+        shapes = dict(edge_i=(np.int32, -1), edge_j=(np.int32, -1), dt=(np.float64, -1), dR=(np.float64, 9),
+                      dv=(np.float64, 3), dp=(np.float64, 3), J_Rg=(np.float64, 9), J_vg=(np.float64, 9),
+                      J_va=(np.float64, 9), J_pg=(np.float64, 9), J_pa=(np.float64, 9), bg_bar=(np.float64, 3),
+                      ba_bar=(np.float64, 3), info=(np.float64, 81), info_bg=(np.float64, -1),
+                      info_ba=(np.float64, -1), v=(np.float64, 3), bg=(np.float64, 3), ba=(np.float64, 3))
+        self.t = {}
+        for k, (dt, m) in shapes.items():
+            a = np.ascontiguousarray(vi[k], dtype=dt)
+            a = a.reshape(-1) if m == -1 else a.reshape(-1, m)
+            self.t[k] = torch.as_tensor(a, device=dev)
+        self.n_edges = int(self.t["edge_i"].shape[0])
+        self.edge_off = None if "edge_off" not in vi else np.ascontiguousarray(vi["edge_off"], dtype=np.int32)
+        ptr = lambda x: x.data_ptr() if x.numel() else None
+        self.I = Inertial(self.n_edges, 0, None if self.edge_off is None else self.edge_off.ctypes.data,
+                          *[ptr(self.t[k]) for k in VI_ARRAYS],
+                          (C.c_double * 12)(*np.asarray(vi["T_cb"], dtype=np.float64).reshape(12).tolist()),
+                          (C.c_double * 3)(*np.asarray(vi["g"], dtype=np.float64).reshape(3).tolist()))
+
+
+class InertialSolver(Solver):
+    """Reusable stereo-inertial solve of a DeviceProblem with its DeviceInertial."""
+
+    def __init__(self, ctx: Context, prob: DeviceProblem, vi: DeviceInertial):
+        torch = prob.torch
+        self.ctx = ctx
+        self.prob = prob
+        self.vi = vi
+        ws = C.c_size_t(0)
+        batch = C.byref(prob.batch) if prob.n_windows > 1 else None
+        ctx._check(ctx.lib.lba_inertial_workspace_size(ctx.handle, C.byref(prob.problem), batch, C.byref(vi.I),
+                                                       C.byref(ws)), "lba_inertial_workspace_size")
+        self.ws_bytes = ws.value
+        self.ws = torch.empty(max(self.ws_bytes, 256) + 256, dtype=torch.uint8, device=prob.device)
+        self.ws_ptr = (self.ws.data_ptr() + 255) // 256 * 256
+        self.T_out = torch.empty_like(prob.T_cw)
+        self.X_out = torch.empty_like(prob.X)
+        self.outlier = torch.empty(prob.obs_kf.shape[0], dtype=torch.uint8, device=prob.device)
+        self.v_out = torch.empty_like(vi.t["v"])
+        self.bg_out = torch.empty_like(vi.t["bg"])
+        self.ba_out = torch.empty_like(vi.t["ba"])
+        self.stats = np.zeros((prob.n_windows, STATS_LEN), dtype=np.float64)
+        self.log_cap = int(ctx.options.trial_log)
+        self.log = (TrialRecord * max(1, self.log_cap * prob.n_windows))()
+        self.result = Result(self.T_out.data_ptr(), self.X_out.data_ptr(), self.outlier.data_ptr(),
+                             self.stats.ctypes.data, C.addressof(self.log) if self.log_cap > 0 else None)
+
+    def run(self, stream=None):
+        torch = self.prob.torch
+        if stream is None:
+            stream = torch.cuda.current_stream(self.prob.device)
+        batch = C.byref(self.prob.batch) if self.prob.n_windows > 1 else None
+        st = self.ctx.lib.lba_solve_inertial(self.ctx.handle, C.byref(self.prob.problem), batch,
+                                             C.byref(self.vi.I), C.byref(self.result), self.v_out.data_ptr(),
+                                             self.bg_out.data_ptr(), self.ba_out.data_ptr(), C.c_void_p(self.ws_ptr),
+                                             C.c_size_t(self.ws_bytes), C.c_void_p(stream.cuda_stream))
+        self.ctx._check(st, "lba_solve_inertial")
+        return self
+
+
+def solve_inertial(data: dict, vi: dict, device="cuda", z_f32: bool = False, **options) -> dict:
+    """One-shot stereo-inertial solve of a window (or a batch with ``edge_off``)."""
+    import torch
+    dev = torch.device(device)
+    ctx = Context(device=dev.index or 0, **options)
+    prob = DeviceProblem(data, device=dev, z_f32=z_f32)
+    dvi = DeviceInertial(vi, device=dev)
+    s = InertialSolver(ctx, prob, dvi).run()
+    out = dict(T=s.T_out.cpu().numpy(), X=s.X_out.cpu().numpy(), V=s.v_out.cpu().numpy(),
+               BG=s.bg_out.cpu().numpy(), BA=s.ba_out.cpu().numpy(),
+               outlier=s.outlier.cpu().numpy().astype(bool), stats=s.stats_dicts(), log=s.trial_logs())
+    ctx.close()
+    return out
 
 
 def solve(data: dict, device="cuda", z_f32: bool = False, **options) -> dict:

@@ -638,3 +638,20 @@ def vi_stereo(seed: int = 7, noise: bool = True) -> tuple[dict, dict]:
     """Stereo-inertial window: 10 optimisable + 5 fixed keyframes on a 4 m walk, 6,000
     points, 8 observations per point (70% stereo): a reduced system of 150 unknowns."""
     return vi_window(seed, K=15, n_fixed=5, M=6000, nobs=(8, 8), stereo_p=0.7, walk_length=4.0, noise=noise)
+
+
+def concat_vi(pairs: list[tuple[dict, dict]]) -> tuple[dict, dict]:
+    """Batch of stereo-inertial windows: the visual windows concatenated (``concat``) and
+    their inertial measurements and states end to end, with ``edge_off`` (keyframe indices
+    stay local to their window)."""
+    w = concat([p[0] for p in pairs])
+    vis = [p[1] for p in pairs]
+    per_edge = ["edge_i", "edge_j", "dt", "dR", "dv", "dp", "J_Rg", "J_vg", "J_va", "J_pg", "J_pa", "bg_bar",
+                "ba_bar", "info", "info_bg", "info_ba"]
+    vi = {k: np.concatenate([np.asarray(x[k]) for x in vis]) for k in per_edge}
+    for k in ("v", "bg", "ba", "v_true", "bg_true", "ba_true"):
+        vi[k] = np.concatenate([x[k] for x in vis])
+    vi["edge_off"] = np.concatenate([[0], np.cumsum([len(x["dt"]) for x in vis])]).astype(np.int32)
+    vi["T_cb"] = vis[0]["T_cb"].copy()
+    vi["g"] = vis[0]["g"].copy()
+    return w, vi

@@ -63,7 +63,8 @@ def test_tuner_table_and_tuned_solve(ref):
     prob = lba.DeviceProblem(cat, device=dev)
     table = ctx.tune(prob)
     print(f"tuned table {table}", flush=True)
-    assert len(table) == 3 and all(v in (64, 128, 256, 512, 1024, 2048, 4096) for v in table)
+    assert len(table) == lba.TUNE_CLASSES and all(v in (64, 128, 256, 512, 1024, 2048, 4096) for v in table)
+    assert ctx.tune_table() == table
     s = lba.Solver(ctx, prob).run()
     from tests.parity import assert_fp64_parity, window_slice
     T, X, fl, st = s.T_out.cpu().numpy(), s.X_out.cpu().numpy(), s.outlier.cpu().numpy().astype(bool), s.stats_dicts()
@@ -71,3 +72,42 @@ def test_tuner_table_and_tuned_solve(ref):
         ks, ps, os_ = window_slice(cat, i)
         r = ref.solve(ws[i])
         assert_fp64_parity(ws[i], T[ks], X[ps], fl[os_], st[i], r)
+
+
+def test_stored_tile_table_is_applied_and_mixed_batches_tune(ref):
+    """A table stored with lba_tune_get and installed in a fresh context with
+    lba_tune_set gives the same tile plan (the same workspace) and a solve at oracle
+    parity; and a batch mixing one large window with many small ones tunes without running
+    out of scratch (the candidate tables' workspaces differ in their update parts)."""
+    ws = _windows()
+    cat = synth.concat(ws)
+    dev = torch.device("cuda:0")
+    a = lba.Context(device=0, precision="fp64")
+    prob = lba.DeviceProblem(cat, device=dev)
+    table = a.tune(prob)
+    b = lba.Context(device=0, precision="fp64")
+    with pytest.raises(lba.LBAError):
+        b.tune_table()
+    b.set_tune_table(table)
+    assert b.tune_table() == table
+    sa = lba.Solver(a, prob).run()
+    sb = lba.Solver(b, lba.DeviceProblem(cat, device=dev)).run()
+    assert sa.ws_bytes == sb.ws_bytes
+    from tests.parity import assert_fp64_parity, window_slice
+    T, X = sb.T_out.cpu().numpy(), sb.X_out.cpu().numpy()
+    fl, st = sb.outlier.cpu().numpy().astype(bool), sb.stats_dicts()
+    for i in (1, 5):
+        ks, ps, os_ = window_slice(cat, i)
+        assert_fp64_parity(ws[i], T[ks], X[ps], fl[os_], st[i], ref.solve(ws[i]))
+    b.set_tune_table(None)
+    with pytest.raises(lba.LBAError):
+        b.tune_table()
+    with pytest.raises(lba.LBAError, match="points per tile"):
+        b.set_tune_table([0] * lba.TUNE_CLASSES)
+    # one window of 5,000 points among 40 of 60
+    big = synth.c5_windows(only=[0], max_points=5000)
+    small = [synth.tiny_window(300 + i, K=6, n_fixed=2, M=60, nobs=(2, 5)) for i in range(40)]
+    mix = synth.concat(big + small)
+    c = lba.Context(device=0, precision="mixed")
+    t2 = c.tune(lba.DeviceProblem(mix, device=dev, z_f32=True))
+    assert len(t2) == lba.TUNE_CLASSES
