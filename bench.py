@@ -629,6 +629,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-window plain FP64 comparison")
     ap.add_argument("--no-tune", action="store_true", help="skip the tile tuner")
+    ap.add_argument("--fp32-accum", action="store_true",
+                    help="mixed workloads: sum the Schur complement in FP32 (the literal precision form)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 256 MiB device to device once (a kernel of known traffic that "
                          "calibrates hardware byte counters read by a profiler)")
@@ -667,7 +669,7 @@ def main():
     mixed = spec["precision"] == "mixed"
     z_f32 = spec["z_f32"]
     dev = torch.device("cuda:0")
-    ctx = lba.Context(device=0, precision=spec["precision"])
+    ctx = lba.Context(device=0, precision=spec["precision"], schur_fp32_accum=1 if args.fp32_accum else 0)
     prob = lba.DeviceProblem(data, device=dev, z_f32=z_f32)
     stream = torch.cuda.current_stream(dev)
     tuned = None
@@ -717,7 +719,8 @@ def main():
     kern = {k: dict(launches=n, total_ms=ms, mean_us=(1e3 * ms / n if n else 0.0)) for k, (n, ms) in prof.items()}
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
     r = kernel_roofs(dom, shapes, kern[dom]["mean_us"], mixed, z_f32)
-    traffic = measured_traffic(args.workload, dom)
+    # the committed counters were taken with the default FP64 Schur sums
+    traffic = measured_traffic(args.workload, dom) if not args.fp32_accum else None
     common = dict(kernel=dom, traffic=traffic, flops_per_launch=r["flops_per_launch"],
                   bytes_per_launch=r["bytes_per_launch"], mean_us=r["mean_us"],
                   alu_TFLOPs=r["achieved_TFLOPs"], alu_frac=r["alu_frac"],
@@ -758,7 +761,8 @@ def main():
                    "keyframes": int(sum(s["K"] for s in shapes)), "points": int(sum(s["M"] for s in shapes)),
                    "observations": int(sum(s["N"] for s in shapes)),
                    "lm_iterations_per_step": iters // args.steps,
-                   "points_per_tile_by_kopt_class": tuned},
+                   "schur_sums": "fp32" if (mixed and args.fp32_accum) else "fp64",
+                   "points_per_tile_by_window_class": tuned},
         "graph_replay": {"value": giters / gel, "ms_per_step": 1e3 * gel / args.steps,
                          "note": "the timed steps repeated with each LM step replayed from its HIP graph "
                                  "(value above: kernels launched one by one between HIP events)"},

@@ -47,15 +47,18 @@ def test_mixed_c2(z_f32):
     _record(f"c2_mixed_zf32={z_f32}", m)
 
 
-def test_mixed_c3_precision_form():
+@pytest.mark.parametrize("acc32", [0, 1], ids=["fp64_sums", "fp32_sums"])
+def test_mixed_c3_precision_form(acc32):
+    """C3 in the mixed form, with the Schur complement summed in FP64 (default) or, the
+    literal precision form, in FP32."""
     w = synth.c3_precision()
-    print(f"case c3 N={len(w['obs_kf'])}", flush=True)
+    print(f"case c3 N={len(w['obs_kf'])} acc32={acc32}", flush=True)
     wr = round_z_f32(w)
-    g = lba.solve(w, device="cuda:0", precision="mixed", z_f32=True)
+    g = lba.solve(w, device="cuda:0", precision="mixed", z_f32=True, schur_fp32_accum=acc32)
     r = lbaref.solve(wr)
     m = assert_mixed_tolerances(wr, g["T"], g["X"], g["stats"][0], r)
     m["flags_differ"] = int((g["outlier"] != r["outlier"]).sum())
-    _record("c3_mixed", m)
+    _record(f"c3_mixed_acc32={acc32}", m)
 
 
 def test_fp64_c3_matches_oracle():
@@ -101,19 +104,27 @@ def _oracle_all(ws, threads=16):
         return list(ex.map(lbaref.solve, ws))
 
 
-def test_c5_full_batch_mixed_every_window(c5):
+@pytest.fixture(scope="module")
+def c5_refs(c5):
+    ws, _ = c5
+    wrs = [round_z_f32(w) for w in ws]
+    return wrs, _oracle_all(wrs)
+
+
+@pytest.mark.parametrize("acc32", [0, 1], ids=["fp64_sums", "fp32_sums"])
+def test_c5_full_batch_mixed_every_window(c5, c5_refs, acc32):
     """All 256 windows of the batch, solved together in the mixed form on FP32
-    measurements, against the oracle on the same FP32-rounded measurements: final cost
-    within 1e-4 relative and RMS reprojection difference within 0.01 px in every window.
+    measurements (Schur complement summed in FP64, or in FP32: the literal precision
+    form), against the oracle on the same FP32-rounded measurements: final cost within
+    1e-4 relative and RMS reprojection difference within 0.01 px in every window.
     Outlier flags may differ where an observation's s lies within the FP32 path's error of
     its threshold; their count is recorded with the other per-result errors."""
     ws, cat = c5
-    print(f"case c5 mixed windows={len(ws)} N={len(cat['obs_kf'])}", flush=True)
-    g = lba.solve(cat, device="cuda:0", precision="mixed", z_f32=True)
+    print(f"case c5 mixed windows={len(ws)} N={len(cat['obs_kf'])} acc32={acc32}", flush=True)
+    g = lba.solve(cat, device="cuda:0", precision="mixed", z_f32=True, schur_fp32_accum=acc32)
     st = g["stats"]
     assert all(s["iters_r1"] >= 1 and s["iters_r2"] >= 1 for s in st)
-    wrs = [round_z_f32(w) for w in ws]
-    refs = _oracle_all(wrs)
+    wrs, refs = c5_refs
     rows = []
     for i, (wr, r) in enumerate(zip(wrs, refs)):
         ks, ps, os_ = window_slice(cat, i)
@@ -124,7 +135,7 @@ def test_c5_full_batch_mixed_every_window(c5):
         rows.append(m)
     worst = max(rows, key=lambda m: m["cost_rel"])
     worst_px = max(rows, key=lambda m: m["rms_px"])
-    _record("c5_mixed_all_windows", dict(
+    _record(f"c5_mixed_all_windows_acc32={acc32}", dict(
         windows=len(rows), cost_rel_max=worst["cost_rel"], cost_rel_worst_window=worst,
         rms_px_max=worst_px["rms_px"], pos_m_max=max(m["pos_m"] for m in rows),
         rot_rad_max=max(m["rot_rad"] for m in rows), flags_differ_total=sum(m["flags_differ"] for m in rows),
