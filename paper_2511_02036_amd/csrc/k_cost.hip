@@ -300,6 +300,10 @@ __global__ __launch_bounds__(kCostRedThreads) void k_cost_reduce(CostArgs a, int
     }
 }
 
+size_t cost_static_lds() {
+    return std::max(kernel_static_lds((const void *)k_cost<true>), kernel_static_lds((const void *)k_cost<false>));
+}
+
 hipError_t launch_cost(const CostArgs &a, int ntiles, int max_k, bool backward, hipStream_t s) {
     if (ntiles <= 0) return hipSuccess;
     const size_t lds = cost_lds_bytes(max_k, backward);

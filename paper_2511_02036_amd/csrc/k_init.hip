@@ -190,6 +190,8 @@ __global__ __launch_bounds__(kInitThreads) void k_init(LinArgs a) {
     }
 }
 
+size_t init_static_lds() { return kernel_static_lds((const void *)k_init); }
+
 hipError_t launch_init(const LinArgs &a, int ntiles, size_t lds, hipStream_t s) {
     if (ntiles <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_init, dim3(ntiles), dim3(kInitThreads), lds, s, a);

@@ -15,7 +15,9 @@
 //   2. the threads of each point sum Hll and bl through LDS, factor
 //      V = Hll + lambda I = L L^T and stage Z_a = W_a L^-T (so W_a V^-1 W_b^T = Z_a Z_b^T);
 //      the observation's own terms D_a = Hpp_a - Z_a Z_a^T and r_a = bp_a - Z_a L^-1 bl go
-//      straight into FP64 per-camera sums in LDS (LDS atomics);
+//      into FP64 per-camera sums in LDS, one copy per wavefront where LDS allows (LDS
+//      atomics from the lanes of one wavefront only, which the hardware applies in a fixed
+//      order), else one copy for the block;
 //   3. every pair (a, b), a < b, of optimisable observations of one point is placed into
 //      a list sorted by camera block: the count of block (kA, kB) is the popcount of the
 //      two camera masks, and a pair's place is the number of the block's points before
@@ -30,14 +32,18 @@
 //      entry of every 14th camera block and add up the contiguous run of their block's
 //      pieces in FP64 registers (no two threads add into the same entry, no atomics
 //      touch S).
-// At the end of the tile each owner writes its entry, plus the per-camera sums on the
-// diagonal blocks, to the tile's partial system; a separate kernel sums the partials of
-// a window in a fixed order (no global atomics).  The per-camera sums of step 2 are
-// accumulated in no fixed order, so results may differ between runs in their last bits.
+// At the end of the tile each owner writes its entry, plus the per-camera sums of the
+// wavefronts in wavefront order on the diagonal blocks, to the tile's partial system; a
+// separate kernel sums the partials of a window in a fixed order (no global atomics).
+// With one copy of the camera sums per wavefront every sum is taken in a fixed order and
+// two runs agree bit for bit, except in chunks with two observations of one point on one
+// camera, whose pairs are placed by atomics of several wavefronts.
 // The gradient bp itself is not needed: the gain-ratio denominator uses
 // dp^T bp = dp^T r + sum_j q_j^T V_j^-1 bl_j (q_j = sum_a W_a^T dp), whose point part
 // the update kernel forms.
 #include "lba_internal.h"
+
+#include <algorithm>
 
 namespace lba {
 
@@ -71,8 +77,11 @@ struct LinSmem {
     int *opt;        // K
     Real *Z;         // CO x ZS (18 values per observation)
     double *hs;      // CO x 9    FP64 Hll_a (6) and bl_a (3) for the point sums
-    double *dacc;    // kMaxOpt x 27: per camera, sum of D_a (lower triangle, 21) and r_a (6)
-    unsigned *pairs; // PCAP pairs, then PCAP + 1 piece starts (list positions)
+    int *ints;       // the chunk's observation ranges and points (phases 1-2)
+    double *dacc;    // copies x Kopt x 27: per copy (wavefront, or one for the block) and
+                     // camera, sum of D_a (lower triangle, 21) and r_a (6)
+    unsigned *pairs; // PCAP pairs
+    unsigned short *pcs;   // PCAP + 1 piece starts (list positions)
     Real *prod;      // PB x PS: signed 6 x 6 sum of each piece of the current batch
     int *cnt;        // kMaxBlocks + 1 pair counts (then list offsets), then kMaxBlocks + 1
                      // piece offsets
@@ -81,7 +90,7 @@ struct LinSmem {
     int *scan;       // 16: per-wavefront totals
     unsigned long long *touch;   // 2 x kGroups: per group, blocks with pairs in the batch, then
                                  // kMaxOpt x 8: per camera, bit mask of the chunk's points it observes
-    double *red;     // 16 x 2
+    double *red;     // 8 x 2
 };
 
 // value of the neighbouring lane: lanes 2k and 2k + 1 exchange (DPP quad permutation
@@ -175,8 +184,11 @@ __device__ __forceinline__ void piece_product(const LinSmem<Real> &sm, int r0, i
 
 static __host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// LDS layout.  Kopt and the number of copies only size the last region (the camera sums),
+// so a window with fewer keyframes than the launch was sized for finds every other region
+// at the same place.
 template <typename Real>
-__host__ __device__ inline size_t lin_carve(unsigned char *base, int K, LinSmem<Real> *s) {
+__host__ __device__ inline size_t lin_carve(unsigned char *base, int K, int Kopt, int copies, LinSmem<Real> *s) {
     using C = LinCfg<Real>;
     size_t o = 0;
     auto take = [&](size_t bytes) { void *p = base ? (void *)(base + o) : nullptr; o = align_up(o + bytes, 16); return p; };
@@ -187,31 +199,35 @@ __host__ __device__ inline size_t lin_carve(unsigned char *base, int K, LinSmem<
     // (513), first observations and indices of its points (512 each) and the point of
     // each observation slot (CO), see the kernel) and the piece products of phase 4 share
     // space
-    constexpr size_t kStage = sizeof(double) * (C::CO * 9) + sizeof(int) * (kNT + 1 + 2 * kNT + C::CO);
+    constexpr size_t kHs = sizeof(double) * C::CO * 9;
+    constexpr size_t kStage = kHs + sizeof(int) * (kNT + 1 + 2 * kNT + C::CO);
     constexpr size_t kProd = sizeof(Real) * C::PB * C::PS;
     void *prod = take(kStage > kProd ? kStage : kProd);
     void *hs = prod;
-    void *dacc = take(sizeof(double) * kMaxOpt * 27);
-    void *pairs = take(sizeof(unsigned) * (2 * C::PCAP + 1));
+    void *ints = base ? static_cast<void *>(static_cast<unsigned char *>(prod) + kHs) : nullptr;
+    void *pairs = take(sizeof(unsigned) * C::PCAP);
+    void *pcs = take(sizeof(unsigned short) * (C::PCAP + 1));
     void *cnt = take(sizeof(int) * 2 * (kMaxBlocks + 1));
     void *cur = take(sizeof(int) * kMaxBlocks);
     void *touch = take(sizeof(unsigned long long) * (2 * kGroups + kMaxOpt * 8));
     void *oka = take(sizeof(int) * C::CO);
     void *scan = take(sizeof(int) * 16);
-    void *red = take(sizeof(double) * 32);
+    void *red = take(sizeof(double) * 2 * (kNT / 64));
+    void *dacc = take(sizeof(double) * copies * Kopt * 27);
     if (s) {
-        s->T = (double *)T; s->opt = (int *)opt; s->Z = (Real *)Z; s->hs = (double *)hs; s->dacc = (double *)dacc;
-        s->pairs = (unsigned *)pairs; s->prod = (Real *)prod; s->cnt = (int *)cnt; s->cur = (int *)cur; s->touch = (unsigned long long *)touch; s->oka = (int *)oka;
+        s->T = (double *)T; s->opt = (int *)opt; s->Z = (Real *)Z; s->hs = (double *)hs; s->ints = (int *)ints;
+        s->dacc = (double *)dacc; s->pairs = (unsigned *)pairs; s->pcs = (unsigned short *)pcs; s->prod = (Real *)prod;
+        s->cnt = (int *)cnt; s->cur = (int *)cur; s->touch = (unsigned long long *)touch; s->oka = (int *)oka;
         s->scan = (int *)scan; s->red = (double *)red;
     }
     return o;
 }
 
-size_t lin_lds_bytes(int K, int n, int waves, bool mixed) {
-    (void)n;
-    (void)waves;
-    return mixed ? lin_carve<float>(nullptr, K, nullptr) : lin_carve<double>(nullptr, K, nullptr);
+size_t lin_lds_bytes(int K, int kopt, int copies, bool mixed) {
+    return mixed ? lin_carve<float>(nullptr, K, kopt, copies, nullptr) : lin_carve<double>(nullptr, K, kopt, copies, nullptr);
 }
+
+int lin_self_copies(bool mixed) { return mixed ? LinCfg<float>::CO / 64 : LinCfg<double>::CO / 64; }
 
 // index of block (ka <= kb) of the upper block triangle, row-major
 __device__ __forceinline__ int block_id(int ka, int kb, int Kopt) { return ka * Kopt - ka * (ka - 1) / 2 + (kb - ka); }
@@ -306,14 +322,14 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
     const int K = W.K, n = W.n, E = W.E, Kopt = W.Kopt;
     const int nblk = Kopt * (Kopt + 1) / 2;
     LinSmem<Real> sm;
-    lin_carve<Real>(smem, K, &sm);
+    lin_carve<Real>(smem, K, Kopt, a.self_copies, &sm);
     unsigned long long *const cm = sm.touch + 2 * kGroups;
-    int *const pst = reinterpret_cast<int *>(sm.hs + C::CO * 9);   // chunk-local observation starts
+    int *const pst = sm.ints;                           // chunk-local observation starts
     int *const gst = pst + kNT + 1;                     // place of each point's first observation
     int *const pid = gst + kNT;                         // global index of each point
     int *const seg = pid + kNT;                         // chunk point of each observation slot
     int *const pco = sm.cnt + kMaxBlocks + 1;           // piece offsets per block
-    unsigned *const pcs = sm.pairs + C::PCAP;           // first list position of each piece
+    unsigned short *const pcs = sm.pcs;                 // first list position of each piece
     const double lambda = ctl.lambda;
     const double *Xs = ctl.cur ? a.X1 : a.X0;
     const int tid = threadIdx.x;
@@ -341,9 +357,11 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             else if (diag && rpos) m_r |= 1ull << k;
         }
     }
-    // per-camera self terms, in the accumulation type (the region is sized for FP64)
+    // camera sums of the self terms, one copy per wavefront that holds observation slots
+    // (CO / 64 copies) or one for the block, in the accumulation type (sized for FP64)
+    const int ncopy = a.self_copies;
     Acc *const dacc = reinterpret_cast<Acc *>(sm.dacc);
-    for (int i = tid; i < Kopt * 27; i += kNT) dacc[i] = (Acc)0;
+    for (int i = tid; i < ncopy * Kopt * 27; i += kNT) dacc[i] = (Acc)0;
     __syncthreads();
 
     const CamParams cam = a.c.cam;
@@ -508,8 +526,8 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
 #pragma unroll
             for (int i = 0; i < 18; ++i) sm.Z[tid * C::ZS + i] = Zr[i];
             // the observation's own term, D_a = Hpp_a - Z_a Z_a^T and r_a = bp_a - Z_a t, goes
-            // straight into its camera's LDS sums
-            Acc *dst = dacc + ka * 27;
+            // into its camera's sums of this wavefront
+            Acc *dst = dacc + ((ncopy > 1 ? tid >> 6 : 0) * Kopt + ka) * 27;
             int e = 0;
 #pragma unroll
             for (int i = 0; i < 6; ++i)
@@ -572,7 +590,7 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             if (tid == nblk - 1) {
                 sm.cnt[nblk] = (int)(incl & 4095u);
                 pco[nblk] = (int)((incl >> sh) & 1023u);
-                pcs[(incl >> sh) & 1023u] = incl & 4095u;
+                pcs[(incl >> sh) & 1023u] = (unsigned short)(incl & 4095u);
             }
         } else {   // pair offsets (low half) and piece offsets (high half) in one scan
             const int c = tid < nblk ? sm.cnt[tid] : 0;
@@ -585,7 +603,7 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             if (tid == nblk - 1) {
                 sm.cnt[nblk] = incl & 0xffff;
                 pco[nblk] = incl >> 16;
-                if (C::kPiece > 1) pcs[incl >> 16] = (unsigned)(incl & 0xffff);
+                if (C::kPiece > 1) pcs[incl >> 16] = (unsigned short)(incl & 0xffff);
             }
         }
         __syncthreads();
@@ -602,7 +620,7 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             sm.pairs[pos] = (unsigned)first | ((unsigned)second << 10) | (fl << 20);
             if (C::kPiece > 1) {
                 const int pq = kp == C::kPiece ? rk / C::kPiece : rk / C::kPieceSmall;
-                if (rk == pq * kp) pcs[pco[B] + pq] = (unsigned)pos;
+                if (rk == pq * kp) pcs[pco[B] + pq] = (unsigned short)pos;
             }
         };
         if (!anydup) {
@@ -696,13 +714,16 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             const int kA = block_row(B, Kopt);
             const int ri = qe <= 5 ? qe - 1 : 5;
             if ((m_r >> k) & 1) {
-                pr[6 * kA + ri] = (double)dacc[kA * 27 + 21 + ri];
+                Acc v = (Acc)0;
+                for (int w = 0; w < ncopy; ++w) v += dacc[(w * Kopt + kA) * 27 + 21 + ri];
+                pr[6 * kA + ri] = (double)v;
                 continue;
             }
             const int kB = kA + (B - block_id(kA, kA, Kopt));
             const int ie = qe / 6, je = qe - 6 * (qe / 6);
             Acc v = acc[k];
-            if (kA == kB) v += dacc[kA * 27 + ie * (ie + 1) / 2 + je];
+            if (kA == kB)
+                for (int w = 0; w < ncopy; ++w) v += dacc[(w * Kopt + kA) * 27 + ie * (ie + 1) / 2 + je];
             const int ra = 6 * kA + ie, col = 6 * kB + je;
             part[ra >= col ? packed_lower(ra, col) : packed_lower(col, ra)] = (double)v;
         }
@@ -743,6 +764,15 @@ hipError_t launch_linearize(const LinArgs &a, int ntiles, size_t lds, bool mixed
         else hipLaunchKernelGGL((k_linearize<double, double, double>), grid, block, lds, s, a);
     }
     return hipGetLastError();
+}
+
+size_t lin_static_lds() {
+    const void *f[6] = {(const void *)k_linearize<float, float, float>, (const void *)k_linearize<float, double, float>,
+                        (const void *)k_linearize<float, float, double>, (const void *)k_linearize<float, double, double>,
+                        (const void *)k_linearize<double, float, double>, (const void *)k_linearize<double, double, double>};
+    size_t m = 0;
+    for (const void *p : f) m = std::max(m, kernel_static_lds(p));
+    return m;
 }
 
 }  // namespace lba

@@ -309,6 +309,8 @@ __global__ __launch_bounds__(kCholThreads) void k_cholesky(CholArgs a) {
     }
 }
 
+size_t chol_static_lds() { return kernel_static_lds((const void *)k_cholesky); }
+
 hipError_t launch_cholesky(const CholArgs &a, int n_windows, size_t lds, hipStream_t s) {
     if (n_windows <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_cholesky, dim3(n_windows), dim3(kCholThreads), lds, s, a);

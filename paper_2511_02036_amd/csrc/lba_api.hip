@@ -88,6 +88,7 @@ struct Plan {
     std::vector<int32_t> opt_map;
     std::vector<int32_t> kf_off, pt_off, obs_off;
     size_t lin_lds = 0, upd_lds = 0, chol_lds = 0, init_lds = 0;
+    int lin_copies = 1;   // copies of the linearisation's camera sums
     int max_En = 0;
     int64_t part_elems = 0;
     int64_t partr_elems = 0;
@@ -290,9 +291,15 @@ lba_status build_plan(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, Pl
             break;
         }
     }
-    if (!pl.waves || lin_lds_bytes(maxK, maxn, 0, pl.mixed) > (size_t)ctx->max_lds)
+    // the linearisation keeps one copy of its camera sums per wavefront (bitwise-repeatable
+    // solves) where LDS allows, else one copy for the block
+    pl.lin_copies = lin_self_copies(pl.mixed);
+    const size_t lin_room = (size_t)ctx->max_lds - std::min((size_t)ctx->max_lds, lin_static_lds());
+    if (lin_lds_bytes(maxK, pl.max_kopt, pl.lin_copies, pl.mixed) > lin_room) pl.lin_copies = 1;
+    if (!pl.waves || lin_lds_bytes(maxK, pl.max_kopt, pl.lin_copies, pl.mixed) > lin_room ||
+        init_lds_bytes(maxK, maxn) + init_static_lds() > (size_t)ctx->max_lds)
         return set_error(ctx, LBA_ERR_UNSUPPORTED, "window of %d keyframes does not fit in LDS", maxK);
-    pl.lin_lds = lin_lds_bytes(maxK, maxn, 0, pl.mixed);
+    pl.lin_lds = lin_lds_bytes(maxK, pl.max_kopt, pl.lin_copies, pl.mixed);
     pl.init_lds = init_lds_bytes(maxK, maxn);
     pl.upd_lds = upd_lds_bytes(maxK, maxn, pl.waves, pl.mixed);
     // the inertial measurements: per window their range, the joint reduced system
@@ -333,7 +340,7 @@ lba_status build_plan(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, Pl
         if (vred > INT32_MAX) return set_error(ctx, LBA_ERR_UNSUPPORTED, "batch too large");
     }
     pl.chol_lds = chol_lds_bytes(maxn);
-    if (pl.chol_lds > (size_t)ctx->max_lds)
+    if (pl.chol_lds + chol_static_lds() > (size_t)ctx->max_lds)
         return set_error(ctx, LBA_ERR_UNSUPPORTED, "reduced system of %d unknowns does not fit in LDS", maxn);
 
     // workspace layout (plan records first: they are uploaded in one copy)
@@ -757,6 +764,7 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
     la.pf = static_cast<double *>(W_(pl.o_pf));
     la.waves = pl.waves;
     la.acc32 = (pl.mixed && opt.schur_fp32_accum) ? 1 : 0;
+    la.self_copies = pl.lin_copies;
     la.c = c;
 
     ReduceArgs ra;
@@ -1055,7 +1063,7 @@ lba_status cost_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, boo
         return set_error(ctx, LBA_ERR_WORKSPACE_TOO_SMALL, "workspace of %zu bytes given, %zu needed", ws_bytes,
                          cp.total);
     if (((uintptr_t)ws) & 255) return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "workspace not 256-byte aligned");
-    if (cost_lds_bytes(cp.maxK, bwd) > (size_t)ctx->max_lds)
+    if (cost_lds_bytes(cp.maxK, bwd) + cost_static_lds() > (size_t)ctx->max_lds)
         return set_error(ctx, LBA_ERR_UNSUPPORTED, "window of %d keyframes does not fit in LDS", cp.maxK);
 
     DeviceGuard dg;

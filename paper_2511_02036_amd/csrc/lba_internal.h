@@ -101,7 +101,8 @@ struct LinArgs {
     int robust;
     int waves;
     int acc32;                   // mixed precision: sum S and the self terms in FP32
-    int pad;
+    int self_copies;             // copies of the camera sums of the self terms: one per
+                                 // wavefront (bitwise-repeatable sums), or 1
     SolveConsts c;
 };
 
@@ -319,7 +320,18 @@ hipError_t launch_cost(const CostArgs &a, int ntiles, int max_k, bool backward, 
 hipError_t launch_cost_reduce(const CostArgs &a, int n_windows, bool backward, hipStream_t s);
 
 // LDS bytes of the linearisation / update blocks for a window shape
-size_t lin_lds_bytes(int K, int n, int waves, bool mixed);
+// The static LDS of a kernel (the runtime's block reductions behind __syncthreads_count
+// and the like take some): it comes on top of the dynamic LDS a launch asks for.
+inline size_t kernel_static_lds(const void *f) {
+    hipFuncAttributes fa;
+    return hipFuncGetAttributes(&fa, f) == hipSuccess ? fa.sharedSizeBytes : 1024;
+}
+size_t lin_static_lds();
+size_t init_static_lds();
+size_t chol_static_lds();
+size_t cost_static_lds();
+size_t lin_lds_bytes(int K, int kopt, int copies, bool mixed);
+int lin_self_copies(bool mixed);   // copies of the camera sums for bitwise-repeatable solves
 size_t upd_lds_bytes(int K, int n, int waves, bool mixed);
 size_t chol_lds_bytes(int n);
 size_t cost_lds_bytes(int K, bool backward);

@@ -25,10 +25,10 @@ def _batch():
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_graph_replays_match_eager_launches(precision):
     """Three solves from captured step graphs (with the program's own GPU work and
-    synchronisations between them) against one solve with kernels launched one by one.
-    The pair lists are ordered by LDS atomics, so two solves agree to rounding, not bit
-    for bit: each replay is held to the FP64 parity bar (cost 1e-9 relative, states
-    1e-8) or, in mixed precision, to 1e-6 relative cost and 1e-6 in the states."""
+    synchronisations between them) against one solve with kernels launched one by one,
+    each replay held to the FP64 parity bar (cost 1e-9 relative, states 1e-8) or, in mixed
+    precision, to 1e-6 relative cost and 1e-6 in the states (bitwise agreement is the next
+    test's)."""
     cat = _batch()
     print(f"case graph precision={precision} obs={len(cat['obs_kf'])}", flush=True)
     dev = torch.device("cuda:0")
@@ -54,6 +54,31 @@ def test_graph_replays_match_eager_launches(precision):
         (x * 2.0 + 1.0).sum().item()
         torch.cuda.synchronize()
 
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_solves_repeat_bit_for_bit(precision):
+    """Every sum of the solve is taken in a fixed order (no point of these windows is seen
+    twice by one keyframe), so two eager solves in separate contexts and two graph
+    replays return the same bits: final cost, iteration counts, poses, points and flags."""
+    cat = _batch()
+    print(f"case repeat precision={precision} obs={len(cat['obs_kf'])}", flush=True)
+    dev = torch.device("cuda:0")
+    runs = []
+    for graphs, reps in ((0, 1), (0, 1), (1, 2)):
+        ctx = lba.Context(device=0, precision=precision, use_graphs=graphs)
+        prob = lba.DeviceProblem(cat, device=dev, z_f32=precision == "mixed")
+        s = lba.Solver(ctx, prob)
+        for _ in range(reps):
+            s.run()
+            torch.cuda.synchronize()
+            runs.append((s.T_out.cpu().numpy(), s.X_out.cpu().numpy(), s.outlier.cpu().numpy(), s.stats.copy()))
+    T0, X0, f0, s0 = runs[0]
+    for i, (T, X, f, st) in enumerate(runs[1:], 1):
+        assert np.array_equal(st, s0), i
+        assert np.array_equal(T, T0), i
+        assert np.array_equal(X, X0), i
+        assert np.array_equal(f, f0), i
 
 def test_tuner_table_and_tuned_solve(ref):
     ws = _windows()
