@@ -184,7 +184,9 @@ lba_status lba_set_options(lba_ctx *ctx, const lba_options *opt);
 
 /* Bytes of DEVICE workspace lba_solve / lba_solve_batch need for this problem
  * (batch NULL: one window).  Limits: per window n_kf <= 128, optimisable keyframes
- * <= 30 (the FP64 reduced system of 180 unknowns is factorised in LDS), at most 64
+ * <= 60 (reduced systems of up to 360 unknowns; above 180 unknowns, or whenever one
+ * window of a batch is that large, the systems are factorised in a copy in HBM rather than
+ * in LDS, and the linearisation makes one pass per 476 camera blocks), at most 64
  * observations per point; beyond them the call returns LBA_ERR_UNSUPPORTED. */
 lba_status lba_workspace_size(lba_ctx *ctx, const lba_problem *problem, const lba_batch *batch,
                               size_t *bytes);

@@ -49,9 +49,8 @@ namespace lba {
 
 constexpr int kNT = kLinThreads;           // 512
 constexpr int kGroups = kLinThreads / 36;  // 14 groups of 36 threads, one block entry each
-constexpr int kSlots = 34;                 // blocks per group (14 * 34 >= 465)
-constexpr int kMaxBlocks = 465;            // Kopt <= 30
-constexpr int kMaxOpt = 30;
+constexpr int kSlots = 34;                 // blocks per group and pass
+constexpr int kPassBlocks = kGroups * kSlots;   // camera blocks per pass (476: Kopt <= 30 in one)
 
 template <typename Real>
 struct LinCfg {
@@ -83,13 +82,13 @@ struct LinSmem {
     unsigned *pairs; // PCAP pairs
     unsigned short *pcs;   // PCAP + 1 piece starts (list positions)
     Real *prod;      // PB x PS: signed 6 x 6 sum of each piece of the current batch
-    int *cnt;        // kMaxBlocks + 1 pair counts (then list offsets), then kMaxBlocks + 1
+    int *cnt;        // pass blocks + 1 pair counts (then list offsets), then pass blocks + 1
                      // piece offsets
-    int *cur;        // kMaxBlocks
+    int *cur;        // pass blocks
     int *oka;        // CO: optimisable camera of the chunk observation (-1: none)
     int *scan;       // 16: per-wavefront totals
     unsigned long long *touch;   // 2 x kGroups: per group, blocks with pairs in the batch, then
-                                 // kMaxOpt x 8: per camera, bit mask of the chunk's points it observes
+                                 // Kopt x 8: per camera, bit mask of the chunk's points it observes
     double *red;     // 8 x 2
 };
 
@@ -184,9 +183,16 @@ __device__ __forceinline__ void piece_product(const LinSmem<Real> &sm, int r0, i
 
 static __host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-// LDS layout.  Kopt and the number of copies only size the last region (the camera sums),
-// so a window with fewer keyframes than the launch was sized for finds every other region
-// at the same place.
+// camera blocks one pass handles (every pass but the last takes kPassBlocks)
+__host__ __device__ inline int pass_blocks(int Kopt) {
+    const int nblk = Kopt * (Kopt + 1) / 2;
+    return nblk < kPassBlocks ? nblk : kPassBlocks;
+}
+
+int lin_passes(int kopt) { return (kopt * (kopt + 1) / 2 + kPassBlocks - 1) / kPassBlocks; }
+
+// LDS layout.  A window with fewer keyframes or optimisable keyframes than the launch was
+// sized for takes less.
 template <typename Real>
 __host__ __device__ inline size_t lin_carve(unsigned char *base, int K, int Kopt, int copies, LinSmem<Real> *s) {
     using C = LinCfg<Real>;
@@ -207,9 +213,10 @@ __host__ __device__ inline size_t lin_carve(unsigned char *base, int K, int Kopt
     void *ints = base ? static_cast<void *>(static_cast<unsigned char *>(prod) + kHs) : nullptr;
     void *pairs = take(sizeof(unsigned) * C::PCAP);
     void *pcs = take(sizeof(unsigned short) * (C::PCAP + 1));
-    void *cnt = take(sizeof(int) * 2 * (kMaxBlocks + 1));
-    void *cur = take(sizeof(int) * kMaxBlocks);
-    void *touch = take(sizeof(unsigned long long) * (2 * kGroups + kMaxOpt * 8));
+    const int nloc = pass_blocks(Kopt);
+    void *cnt = take(sizeof(int) * 2 * (nloc + 1));
+    void *cur = take(sizeof(int) * (nloc > 0 ? nloc : 1));
+    void *touch = take(sizeof(unsigned long long) * (2 * kGroups + 8 * (Kopt > 0 ? Kopt : 1)));
     void *oka = take(sizeof(int) * C::CO);
     void *scan = take(sizeof(int) * 16);
     void *red = take(sizeof(double) * 2 * (kNT / 64));
@@ -320,7 +327,14 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
     const Ctl ctl = a.ctl[tile.win];
     if (!ctl.running) return;
     const int K = W.K, n = W.n, E = W.E, Kopt = W.Kopt;
-    const int nblk = Kopt * (Kopt + 1) / 2;
+    // pass blockIdx.y owns the camera blocks [bbase, bbase + nblk) of the upper block
+    // triangle (row-major); its lists, offsets and owner slots use block indices local to
+    // the pass
+    const int bbase = blockIdx.y * kPassBlocks;
+    const int nall = Kopt * (Kopt + 1) / 2;
+    if (bbase > 0 && bbase >= nall) return;
+    const int nblk = nall - bbase < kPassBlocks ? nall - bbase : kPassBlocks;
+    const bool first_pass = blockIdx.y == 0;
     LinSmem<Real> sm;
     lin_carve<Real>(smem, K, Kopt, a.self_copies, &sm);
     unsigned long long *const cm = sm.touch + 2 * kGroups;
@@ -328,7 +342,7 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
     int *const gst = pst + kNT + 1;                     // place of each point's first observation
     int *const pid = gst + kNT;                         // global index of each point
     int *const seg = pid + kNT;                         // chunk point of each observation slot
-    int *const pco = sm.cnt + kMaxBlocks + 1;           // piece offsets per block
+    int *const pco = sm.cnt + pass_blocks(Kopt) + 1;    // piece offsets per block
     unsigned short *const pcs = sm.pcs;                 // first list position of each piece
     const double lambda = ctl.lambda;
     const double *Xs = ctl.cur ? a.X1 : a.X0;
@@ -338,8 +352,8 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
     for (int i = tid; i < K; i += kNT) sm.opt[i] = a.opt_map[W.kf0 + i];
 
     // ---- owned entries: thread g * 36 + q (g < 14) owns entry q = 6 i + j of the 6 x 6
-    // blocks B = g + 14 k (kA <= kB).  In a diagonal block the entries j <= i are S, the six
-    // upper positions 1 2 3 4 5 8 accumulate r of that camera, the rest are unused.
+    // blocks bbase + g + 14 k (kA <= kB).  In a diagonal block the entries j <= i are S, the
+    // six upper positions 1 2 3 4 5 8 accumulate r of that camera, the rest are unused.
     const int grp = tid / 36, qe = tid - 36 * grp;
     const int nent = nblk;
     Acc acc[kSlots];
@@ -351,8 +365,8 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
         const bool rpos = qe == 8 || (qe >= 1 && qe <= 5);
         for (int k = 0; k < kSlots; ++k) {
             const int B = grp + kGroups * k;
-            const int kA = block_row(B, Kopt);
-            const bool diag = B == block_id(kA, kA, Kopt);
+            const int kA = block_row(bbase + B, Kopt);
+            const bool diag = bbase + B == block_id(kA, kA, Kopt);
             if (grp >= kGroups || B >= nent || (diag && je > ie && !rpos)) m_skip |= 1ull << k;
             else if (diag && rpos) m_r |= 1ull << k;
         }
@@ -490,7 +504,7 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             V[5] += lambda;
             if (!chol3_inv<double>(V, Li)) fail = 1;
             lmul<double>(Li, bs[0], bs[1], bs[2], t0, t1, t2);
-            if (tid == s0) {   // the point's factor, for this step's back-substitution
+            if (tid == s0 && first_pass) {   // the point's factor, for this step's back-substitution
                 double *f = a.pf + 12 * (int64_t)pid[pl];
 #pragma unroll
                 for (int i = 0; i < 6; ++i) f[i] = Li[i];
@@ -550,7 +564,8 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
         const int nwrd = (q - p + 63) >> 6;
         if (!anydup) {
             for (int B = tid; B < nblk; B += kNT) {
-                const int kA = block_row(B, Kopt), kB = kA + (B - block_id(kA, kA, Kopt));
+                const int Bg = bbase + B;
+                const int kA = block_row(Bg, Kopt), kB = kA + (Bg - block_id(kA, kA, Kopt));
                 int c = 0;
                 if (kA != kB)
                     for (int w = 0; w < nwrd; ++w) c += __popcll(cm[kA * 8 + w] & cm[kB * 8 + w]);
@@ -563,8 +578,10 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
                 for (int u = 0; u < 4; ++u) kb[u] = b0 + u < s1 ? sm.oka[b0 + u] : -1;
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
-                    if (kb[u] >= 0)
-                        atomicAdd(&sm.cnt[ka <= kb[u] ? block_id(ka, kb[u], Kopt) : block_id(kb[u], ka, Kopt)], 1);
+                    if (kb[u] >= 0) {
+                        const int Bl = (ka <= kb[u] ? block_id(ka, kb[u], Kopt) : block_id(kb[u], ka, Kopt)) - bbase;
+                        if (Bl >= 0 && Bl < nblk) atomicAdd(&sm.cnt[Bl], 1);
+                    }
             }
         }
         __syncthreads();
@@ -573,8 +590,8 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             // pair offsets (bits 0-11, at most PCAP = 3072), piece offsets for kPieceSmall
             // (bits 12-21) and for kPiece (bits 22-31) in one scan: a block of c pairs has
             // at most c / kPiece + 1 pieces, so each piece field stays below
-            // PCAP / kPieceSmall + kMaxBlocks = 977 < 1024
-            static_assert(C::PCAP < 4096 && C::PCAP / C::kPieceSmall + kMaxBlocks < 1024, "scan fields");
+            // PCAP / kPieceSmall + kPassBlocks = 988 < 1024
+            static_assert(C::PCAP < 4096 && C::PCAP / C::kPieceSmall + kPassBlocks < 1024, "scan fields");
             const unsigned c = tid < nblk ? (unsigned)sm.cnt[tid] : 0u;
             const unsigned v = c | (((c + C::kPieceSmall - 1) / C::kPieceSmall) << 12) |
                                (((c + C::kPiece - 1) / C::kPiece) << 22);
@@ -640,16 +657,19 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
                     const int kA = sm.oka[sa], kB = sm.oka[sb];
                     if (kA < 0 || kB < 0) continue;
                     const int lo = min(kA, kB), hi = max(kA, kB);
+                    const int Bl = block_id(lo, hi, Kopt) - bbase;   // another pass's block
+                    if (Bl < 0 || Bl >= nblk) continue;
                     int r = __popcll(cm[lo * 8 + pw] & cm[hi * 8 + pw] & below);
                     for (int w = 0; w < pw; ++w) r += __popcll(cm[lo * 8 + w] & cm[hi * 8 + w]);
-                    place(sa, sb, kA, kB, r, block_id(lo, hi, Kopt));
+                    place(sa, sb, kA, kB, r, Bl);
                 }
             }
         } else if (ka >= 0) {
             for (int b = tid + 1; b < s1; ++b) {
                 const int kb = sm.oka[b];
                 if (kb < 0) continue;
-                const int B = block_id(min(ka, kb), max(ka, kb), Kopt);
+                const int B = block_id(min(ka, kb), max(ka, kb), Kopt) - bbase;
+                if (B < 0 || B >= nblk) continue;
                 place(tid, b, ka, kb, atomicAdd(&sm.cur[B], 1), B);
             }
         }
@@ -669,7 +689,7 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
                     Real *out = sm.prod + (pi - b0) * C::PS;
                     if (h == 0) {   // the first piece of a block in this batch marks the block
                         const int ka = sm.oka[e & 1023], kb = sm.oka[(e >> 10) & 1023];
-                        const int B = block_id(ka, kb, Kopt);
+                        const int B = block_id(ka, kb, Kopt) - bbase;
                         if (pi == b0 || pi == pco[B])
                             __hip_atomic_fetch_or(&touch[B % kGroups], 1ull << (B / kGroups), __ATOMIC_RELAXED,
                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -710,7 +730,7 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
 #pragma unroll
         for (int k = 0; k < kSlots; ++k) {
             if ((m_skip >> k) & 1) continue;
-            const int B = grp + kGroups * k;
+            const int B = bbase + grp + kGroups * k;
             const int kA = block_row(B, Kopt);
             const int ri = qe <= 5 ? qe - 1 : 5;
             if ((m_r >> k) & 1) {
@@ -735,7 +755,7 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
         sm.red[(tid >> 6) * 2 + 1] = 0.0;
     }
     __syncthreads();
-    if (tid == 0) {
+    if (tid == 0 && first_pass) {
         double F = 0.0, md = 0.0;
         for (int w = 0; w < kNT / 64; ++w) {
             F += sm.red[w * 2];
@@ -749,9 +769,9 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
     (void)E;
 }
 
-hipError_t launch_linearize(const LinArgs &a, int ntiles, size_t lds, bool mixed, hipStream_t s) {
+hipError_t launch_linearize(const LinArgs &a, int ntiles, int passes, size_t lds, bool mixed, hipStream_t s) {
     if (ntiles <= 0) return hipSuccess;
-    dim3 grid(ntiles), block(kNT);
+    dim3 grid(ntiles, passes > 0 ? passes : 1), block(kNT);
     const bool zf = a.obs.z_f32 != 0;
     if (mixed && a.acc32) {   // the literal precision form: S summed in FP32
         if (zf) hipLaunchKernelGGL((k_linearize<float, float, float>), grid, block, lds, s, a);

@@ -10,9 +10,10 @@
 // camera blocks in any order, keep the index order (k_order_identity writes it; the
 // sort did not pay there in measurements).  The others use two kernels, run once per
 // solve after the input checks:
-//   k_order_keys  grid (x, window), one thread per point: key = lowest | highest << 5;
+//   k_order_keys  grid (x, window), one thread per point: key = lowest | highest << 6
+//                 (Kopt for both when no optimisable keyframe observes the point);
 //   k_order       one 1024-thread block per window: two stable counting-sort passes over
-//                 32 buckets (by the highest, then by the lowest), each ranking a round
+//                 Kopt + 1 buckets (by the highest, then by the lowest), each ranking a round
 //                 of 1024 points with one ballot per bucket per wavefront.  The window's
 //                 keys are staged in LDS when they fit.  The second pass writes, per
 //                 position of the order, the point, its first observation and its
@@ -29,14 +30,14 @@ namespace lba {
 
 constexpr int kOrdThreads = 1024;
 constexpr int kOrdWaves = kOrdThreads / kWave;
-constexpr int kBuckets = 32;             // optimisable keyframe index (below 30); 31 = none
+constexpr int kBuckets = 64;             // digit range: optimisable keyframe index, Kopt = none
 constexpr int kOrdLdsPoints = 49152;     // windows up to this many points sort from LDS keys
 constexpr int kSortMinKopt = 20;         // windows with more optimisable keyframes are sorted
 
 __device__ __forceinline__ bool sorted_window(const OrderArgs &a, const WinInfo &W) {
     return a.by_keyframes && W.Kopt > kSortMinKopt;
 }
-static_assert(kMaxKoptFP64 < kBuckets - 1 && kMaxKoptMixed < kBuckets - 1, "keyframe digit range");
+static_assert(kMaxKoptFP64 < kBuckets && kMaxKoptMixed < kBuckets, "keyframe digit range");
 
 __global__ __launch_bounds__(256) void k_order_identity(OrderArgs a) {
     const WinInfo W = a.win[blockIdx.y];
@@ -54,7 +55,8 @@ __global__ __launch_bounds__(256) void k_order_keys(OrderArgs a) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < W.M; i += gridDim.x * blockDim.x) {
         const int P = W.pt0 + i;
         const int o0 = a.pt_start[P], o1 = a.pt_start[P + 1];
-        int lo = kBuckets - 1, hi = 0;
+        const int none = W.Kopt;
+        int lo = none, hi = 0;
         for (int o = o0; o < o1; o += 4) {   // four observations per step: independent loads
             int kf[4];
 #pragma unroll
@@ -68,19 +70,20 @@ __global__ __launch_bounds__(256) void k_order_keys(OrderArgs a) {
                 }
             }
         }
-        if (lo == kBuckets - 1) hi = kBuckets - 1;
-        a.keys[P] = (uint16_t)(lo | (hi << 5));
+        if (lo == none) hi = none;
+        a.keys[P] = (uint16_t)(lo | (hi << 6));
     }
 }
 
 // one stable counting-sort pass over the window's M points: element i of the input order
-// is src[i] (window-local; the identity without src), its bucket the 5-bit digit of its
-// key at bit sh.  The element goes to place pos of the output: dst[pos] (window-local),
+// is src[i] (window-local; the identity without src), its bucket the 6-bit digit of its
+// key at bit sh (below nb = Kopt + 1).  The element goes to place pos of the output: dst[pos] (window-local),
 // or, in the last pass, pinfo[pos].
 template <bool kLast>
 __device__ void order_pass(const OrderArgs &a, const WinInfo &W, const uint16_t *key, const int32_t *src,
                            int32_t *dst, int sh, int *base, int *wcnt) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, M = W.M;
+    const int nb = W.Kopt + 1;
     if (tid < kBuckets) base[tid] = 0;
     __syncthreads();
     for (int i = tid; i < M; i += kOrdThreads) {
@@ -90,7 +93,7 @@ __device__ void order_pass(const OrderArgs &a, const WinInfo &W, const uint16_t 
     __syncthreads();
     if (tid == 0) {
         int s = 0;
-        for (int b = 0; b < kBuckets; ++b) {
+        for (int b = 0; b < nb; ++b) {
             const int c = base[b];
             base[b] = s;
             s += c;
@@ -108,7 +111,7 @@ __device__ void order_pass(const OrderArgs &a, const WinInfo &W, const uint16_t 
             pe = a.pt_start[W.pt0 + e + 1];
         }
         int rank = 0, mine = 0;
-        for (int b = 0; b < kBuckets; ++b) {
+        for (int b = 0; b < nb; ++b) {
             const unsigned long long bal = __ballot(d == b);
             if (d == b) rank = __popcll(bal & ((1ull << lane) - 1ull));
             if (lane == b) mine = __popcll(bal);
@@ -145,7 +148,7 @@ __global__ __launch_bounds__(kOrdThreads) void k_order(OrderArgs a) {
     }
     __syncthreads();
     int32_t *tmp = a.tmp + W.pt0;
-    order_pass<false>(a, W, key, nullptr, tmp, 5, base, wcnt);   // by the highest keyframe
+    order_pass<false>(a, W, key, nullptr, tmp, 6, base, wcnt);   // by the highest keyframe
     __syncthreads();
     order_pass<true>(a, W, key, tmp, nullptr, 0, base, wcnt);    // then, stably, by the lowest
     __syncthreads();

@@ -3,6 +3,8 @@
 // Marquardt decision (gain ratio, accept / reject, damping update, pose retraction).
 #include "lba_internal.h"
 
+#include <algorithm>
+
 namespace lba {
 
 // ------------------------------------------------------------------------------------
@@ -69,6 +71,9 @@ hipError_t launch_reduce(const ReduceArgs &a, int n_windows, hipStream_t s) {
 // panel's 8 entries of y redundantly, and the thread of each row below subtracts its
 // share.  The backward solve walks the panels from the last, every thread solving the
 // panel's 8 entries from prefetched registers, then all threads updating the rows above.
+// A system too large for LDS (n above about 180) is factored the same way in a per-window
+// copy in HBM (kHbm), which one block keeps hot in its XCD's L2; the right side, the
+// pivots and the factored diagonal blocks stay in LDS.
 // ------------------------------------------------------------------------------------
 #ifndef LBA_CHOL_NB
 #define LBA_CHOL_NB 8
@@ -80,6 +85,8 @@ size_t chol_lds_bytes(int n) {
     const size_t E = (size_t)n * (n + 1) / 2;
     return sizeof(double) * (E + 3 * (size_t)n + (size_t)kNB * n) + 64;
 }
+
+size_t chol_lds_bytes_hbm(int n) { return sizeof(double) * (3 * (size_t)n + (size_t)kNB * n) + 64; }
 
 __device__ __forceinline__ void tri_decode(int e, int &ii, int &jj) {
     int r = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
@@ -123,6 +130,7 @@ __device__ __forceinline__ bool diag_block_factor(const double *A, int c0, int n
     return ok;
 }
 
+template <bool kHbm>
 __global__ __launch_bounds__(kCholThreads) void k_cholesky(CholArgs a) {
     extern __shared__ __align__(16) double cs[];
     __shared__ int s_fail;
@@ -134,8 +142,8 @@ __global__ __launch_bounds__(kCholThreads) void k_cholesky(CholArgs a) {
     const int tid = threadIdx.x, lane = tid & 63;
     const int nth = blockDim.x;
     const double lambda = ctl->lambda;
-    double *A = cs;          // E, packed lower
-    double *y = cs + E;      // n: right side, then the solution
+    double *A = kHbm ? a.fact + W.red_off : cs;   // E, packed lower
+    double *y = kHbm ? cs : cs + E;               // n: right side, then the solution
     double *rr = y + n;      // n: copy of the right side (gain-ratio denominator)
     double *rdiag = rr + n;  // n reciprocal pivots
     double *Ld = rdiag + n;  // n x kNB: factored diagonal blocks (row r holds L[r][c0 .. r])
@@ -309,11 +317,14 @@ __global__ __launch_bounds__(kCholThreads) void k_cholesky(CholArgs a) {
     }
 }
 
-size_t chol_static_lds() { return kernel_static_lds((const void *)k_cholesky); }
+size_t chol_static_lds() {
+    return std::max(kernel_static_lds((const void *)k_cholesky<false>), kernel_static_lds((const void *)k_cholesky<true>));
+}
 
 hipError_t launch_cholesky(const CholArgs &a, int n_windows, size_t lds, hipStream_t s) {
     if (n_windows <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_cholesky, dim3(n_windows), dim3(kCholThreads), lds, s, a);
+    if (a.fact) hipLaunchKernelGGL(k_cholesky<true>, dim3(n_windows), dim3(kCholThreads), lds, s, a);
+    else hipLaunchKernelGGL(k_cholesky<false>, dim3(n_windows), dim3(kCholThreads), lds, s, a);
     return hipGetLastError();
 }
 
@@ -413,7 +424,7 @@ hipError_t launch_decide(const DecideArgs &a, int n_windows, hipStream_t s) {
 // ------------------------------------------------------------------------------------
 // damping initialisation of a round: F and lambda0 = tau * max diag(H)
 // ------------------------------------------------------------------------------------
-constexpr int kInitCols = 192;   // columns of one window's r (n = 6 Kopt <= 180), three per lane
+constexpr int kInitCols = 384;   // columns of one window's r (n = 6 Kopt <= 360), six per lane
 constexpr int kInitRedThreads = 1024;
 constexpr int kInitRedWaves = kInitRedThreads / 64;
 
@@ -425,8 +436,8 @@ __global__ __launch_bounds__(kInitRedThreads) void k_init_reduce(InitReduceArgs 
     Ctl *ctl = a.ctl + w;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // largest diagonal entry of Hpp (per camera, summed over the tiles): wavefront g sums
-    // the tiles g, g + G, ... (G wavefronts, four tiles per step: twelve loads in flight),
-    // lane l the columns l, l + 64, l + 128 (coalesced rows) ...
+    // the tiles g, g + G, ... (G wavefronts, four tiles per step), lane l the columns l,
+    // l + 64, ... (coalesced rows) ...
     constexpr int G = kInitRedWaves;
     double cs[kInitCols / 64] = {};
     const double *pr = a.partr + W.partr_off;

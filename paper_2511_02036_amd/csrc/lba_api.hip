@@ -88,6 +88,8 @@ struct Plan {
     std::vector<int32_t> opt_map;
     std::vector<int32_t> kf_off, pt_off, obs_off;
     size_t lin_lds = 0, upd_lds = 0, chol_lds = 0, init_lds = 0;
+    bool chol_hbm = false;   // reduced systems factored in HBM (too large for LDS)
+    int lin_passes = 1;      // linearisation passes over the camera blocks
     int lin_copies = 1;   // copies of the linearisation's camera sums
     int max_En = 0;
     int64_t part_elems = 0;
@@ -96,7 +98,7 @@ struct Plan {
     int64_t dp_elems = 0;
     // workspace byte offsets
     size_t o_win, o_tiles, o_order, o_opt, o_kfoff, o_ptoff, o_obsoff, o_upload_end;
-    size_t o_ptstart, o_ctl, o_T, o_X0, o_X1, o_part, o_partr, o_partd, o_partu, o_red, o_redflag, o_dp, o_pf,
+    size_t o_ptstart, o_ctl, o_T, o_X0, o_X1, o_part, o_partr, o_partd, o_partu, o_red, o_fact, o_redflag, o_dp, o_pf,
         o_pkey, o_ptmp, o_pinfo, o_skf, o_stype, o_soct, o_sz, o_smask, o_stats, o_err, o_log, total;
     int log_cap = 0;
     // stereo-inertial solve
@@ -339,9 +341,13 @@ lba_status build_plan(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, Pl
         }
         if (vred > INT32_MAX) return set_error(ctx, LBA_ERR_UNSUPPORTED, "batch too large");
     }
+    // the reduced system is factored in LDS when it fits, else in a per-window copy in HBM
     pl.chol_lds = chol_lds_bytes(maxn);
-    if (pl.chol_lds + chol_static_lds() > (size_t)ctx->max_lds)
+    pl.chol_hbm = pl.chol_lds + chol_static_lds() > (size_t)ctx->max_lds;
+    if (pl.chol_hbm) pl.chol_lds = chol_lds_bytes_hbm(maxn);
+    if (pl.chol_lds + chol_static_lds() > (size_t)ctx->max_lds || (pl.chol_hbm && pl.vi))
         return set_error(ctx, LBA_ERR_UNSUPPORTED, "reduced system of %d unknowns does not fit in LDS", maxn);
+    pl.lin_passes = lin_passes(pl.max_kopt);
 
     // workspace layout (plan records first: they are uploaded in one copy)
     size_t o = 0;
@@ -375,6 +381,7 @@ lba_status build_plan(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, Pl
     }
     pl.o_partu = o;   o = align256(o + sizeof(double) * 4 * pl.upd_split * std::max<size_t>(pl.tiles.size(), 1));
     pl.o_red = o;     o = align256(o + sizeof(double) * pl.red_elems);
+    pl.o_fact = o;    o = align256(o + (pl.chol_hbm ? sizeof(double) * pl.red_elems : 0));
     pl.o_redflag = o; o = align256(o + sizeof(double) * nw);
     pl.o_dp = o;      o = align256(o + sizeof(double) * pl.dp_elems);
     pl.o_pf = o;      o = align256(o + sizeof(double) * 12 * std::max(P->n_pt, 1));
@@ -785,6 +792,7 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
     ca.red = d_red;
     ca.redflag = d_redflag;
     ca.dp = d_dp;
+    ca.fact = pl.chol_hbm ? static_cast<double *>(W_(pl.o_fact)) : nullptr;
     if (pl.vi) {   // the joint reduced system of 15 Kopt unknowns per window
         ca.win = va.vwin;
         ca.red = va.vred;
@@ -876,7 +884,7 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
         auto step = [&](hipStream_t q) -> hipError_t {
             hipError_t e;
             if ((e = timed(ctx, LBA_KCLASS_LINEARIZE, q,
-                           [&] { return launch_linearize(la, ntiles, pl.lin_lds, pl.mixed, q); })) != hipSuccess)
+                           [&] { return launch_linearize(la, ntiles, pl.lin_passes, pl.lin_lds, pl.mixed, q); })) != hipSuccess)
                 return e;
             if ((e = timed(ctx, LBA_KCLASS_REDUCE, q, [&] { return launch_reduce(ra, nw, q); })) != hipSuccess) return e;
             if (pl.vi) {

@@ -12,8 +12,8 @@ constexpr int kWave = 64;
 constexpr int kMaxObsPerPoint = 64;   // a point's observations fit one wavefront
 constexpr int kMaxKf = 128;           // keyframes per window (poses are staged in LDS)
 constexpr int kMaxLevels = 32;
-constexpr int kMaxKoptFP64 = 30;
-constexpr int kMaxKoptMixed = 30;   // the FP64 reduced system must fit in LDS
+constexpr int kMaxKoptFP64 = 60;
+constexpr int kMaxKoptMixed = 60;   // reduced systems of up to 360 unknowns (in HBM above 180)
 constexpr int kLinThreads = 512;      // linearisation block (owner-computes reduced system)
 constexpr int kUpdThreads = 256;      // update block: 4 wavefronts
 
@@ -156,6 +156,8 @@ struct CholArgs {
     const double *red;
     const double *redflag;
     double *dp;
+    double *fact;   // systems too large for LDS: per window E doubles at red_off, factored in
+                    // place (nullptr: the system is factored in LDS)
 };
 
 struct UpdArgs {
@@ -303,11 +305,13 @@ hipError_t launch_vi_system(const ViArgs &a, int n_windows, hipStream_t s);
 hipError_t launch_vi_split(const ViArgs &a, int n_windows, hipStream_t s);
 hipError_t launch_vi_finish(const ViArgs &a, hipStream_t s);
 
-hipError_t launch_linearize(const LinArgs &a, int ntiles, size_t lds, bool mixed, hipStream_t s);
+hipError_t launch_linearize(const LinArgs &a, int ntiles, int passes, size_t lds, bool mixed, hipStream_t s);
+int lin_passes(int kopt);   // passes over the camera blocks of a window with kopt optimisable keyframes
 hipError_t launch_update(const UpdArgs &a, int ntiles, size_t lds, bool mixed, hipStream_t s);
 hipError_t launch_init(const LinArgs &a, int ntiles, size_t lds, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs &a, int n_windows, hipStream_t s);
 hipError_t launch_cholesky(const CholArgs &a, int n_windows, size_t lds, hipStream_t s);
+size_t chol_lds_bytes_hbm(int n);   // LDS of the variant whose matrix is in HBM
 hipError_t launch_decide(const DecideArgs &a, int n_windows, hipStream_t s);
 hipError_t launch_init_reduce(const InitReduceArgs &a, int n_windows, hipStream_t s);
 hipError_t launch_setup(const MiscArgs &a, int n_windows, hipStream_t s);

@@ -174,12 +174,13 @@ def test_large_tiles_split_across_update_blocks(precision):
 
 
 def test_size_limits_are_rejected_before_any_solve():
-    """31 optimisable keyframes exceed the reduced system's limit of 30 (both
+    """61 optimisable keyframes exceed the reduced system's limit of 60 (both
     precisions); a point with 65 observations exceeds one wavefront.  Both are refused
-    with a message, and the largest accepted case (30) is solved by the C3 tests."""
-    w = synth.tiny_window(30, K=33, n_fixed=2, M=120, nobs=(3, 6), stereo_p=0.5)
+    with a message; the largest accepted case (60) is solved in
+    tests/test_gpu_large_windows.py."""
+    w = synth.tiny_window(30, K=63, n_fixed=2, M=120, nobs=(3, 6), stereo_p=0.5)
     for precision in ("fp64", "mixed"):
-        with pytest.raises(lba.LBAError, match="31 optimisable keyframes"):
+        with pytest.raises(lba.LBAError, match="61 optimisable keyframes"):
             _gpu(w, precision=precision)
     w = synth.tiny_window(31, K=5, n_fixed=2, M=20, nobs=(2, 4), stereo_p=0.5)
     first = np.flatnonzero(w["obs_pt"] == 0)[0]
