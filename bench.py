@@ -145,6 +145,11 @@ def kernel_bytes_and_flops(cls, s, z_bytes):
         return N * obs_rec + M * 48, FLOP_TRIAL * N
     if cls == "linearize_init":
         return N * obs_rec + M * 24, res_hess
+    if cls == "cholesky":
+        # the reduced system of n = 6 Kopt unknowns: factorisation n^3 / 3 plus the forward and
+        # back solves 2 n^2 flops (FP64), its packed triangle and right side read once
+        n = 6 * s["Kopt"]
+        return 8 * (n * (n + 1) // 2 + n), n ** 3 / 3.0 + 2.0 * n * n
     return 0, 0
 
 
@@ -179,7 +184,7 @@ def kernel_roofs(cls, shapes, mean_us, mixed, z_f32):
     sec = mean_us * 1e-6
     gbs = tb / sec / 1e9 if sec > 0 else 0.0
     tfs = tf / sec / 1e12 if sec > 0 else 0.0
-    peak = FP32_PEAK_TFLOPS if mixed else FP64_PEAK_TFLOPS
+    peak = FP32_PEAK_TFLOPS if (mixed and cls != "cholesky") else FP64_PEAK_TFLOPS
     return dict(bytes_per_launch=tb, flops_per_launch=tf, mean_us=mean_us, achieved_GBs=gbs,
                 hbm_frac=gbs / HBM_PEAK_GBS, achieved_TFLOPs=tfs, alu_peak=peak, alu_frac=tfs / peak,
                 alu_frac_nonpacked=tfs / NONPACKED_PEAK_TFLOPS)
