@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define LBA_ABI_VERSION 3
+#define LBA_ABI_VERSION 4
 
 typedef enum {
     LBA_OK = 0,
@@ -87,6 +87,11 @@ typedef struct {
     int32_t schur_fp32_accum; /* mixed precision only: 1 = sum the Schur complement and the
                                  per-camera terms in FP32 (the literal precision form), 0 = in
                                  FP64 from the FP32 products [0] */
+    int32_t pair_cache;      /* 1: the linearisation keeps the pair structure of the Schur
+                                complement (which observations of a point pair up on which
+                                camera block) in the workspace for the rest of an LM round, so
+                                that only the first step of a round forms it; 0: formed at
+                                every step.  The results are the same [1] */
 } lba_options;
 
 typedef struct {

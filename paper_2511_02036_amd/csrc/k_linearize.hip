@@ -90,6 +90,7 @@ struct LinSmem {
     unsigned long long *touch;   // 2 x kGroups: per group, blocks with pairs in the batch, then
                                  // Kopt x 8: per camera, bit mask of the chunk's points it observes
     double *red;     // 8 x 2
+    int *rec;        // 4: word offset of the chunk's record in the pool (-1: not stored)
 };
 
 // value of the neighbouring lane: lanes 2k and 2k + 1 exchange (DPP quad permutation
@@ -221,11 +222,12 @@ __host__ __device__ inline size_t lin_carve(unsigned char *base, int K, int Kopt
     void *scan = take(sizeof(int) * 16);
     void *red = take(sizeof(double) * 2 * (kNT / 64));
     void *dacc = take(sizeof(double) * copies * Kopt * 27);
+    void *rec = take(sizeof(int) * 4);
     if (s) {
         s->T = (double *)T; s->opt = (int *)opt; s->Z = (Real *)Z; s->hs = (double *)hs; s->ints = (int *)ints;
         s->dacc = (double *)dacc; s->pairs = (unsigned *)pairs; s->pcs = (unsigned short *)pcs; s->prod = (Real *)prod;
         s->cnt = (int *)cnt; s->cur = (int *)cur; s->touch = (unsigned long long *)touch; s->oka = (int *)oka;
-        s->scan = (int *)scan; s->red = (double *)red;
+        s->scan = (int *)scan; s->red = (double *)red; s->rec = (int *)rec;
     }
     return o;
 }
@@ -347,6 +349,22 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
     const double lambda = ctl.lambda;
     const double *Xs = ctl.cur ? a.X1 : a.X0;
     const int tid = threadIdx.x;
+    // Chunk records.  The pairs of a chunk, their pieces and the blocks' piece offsets
+    // depend only on which observations are active, which is fixed within an LM round.
+    // The first launch of a round forms them (phases 1-3 below) and stores one record per
+    // chunk in the pool while it has room; later launches of the round load the records
+    // instead of forming them.  A record: next record (word offset, ~0 for none), end
+    // point of the chunk, pairs | pieces << 12 | (pieces of kPieceSmall) << 22, place of
+    // the chunk's first observation; then the pairs, the piece starts (16-bit) and the
+    // blocks' piece offsets (16-bit).
+    const int slot = t * (int)gridDim.y + (int)blockIdx.y;
+    const int head = a.plan_head ? a.plan_head[slot] : -1;
+    const bool use = head >= 0;
+    bool store = !use && a.plan_head != nullptr;   // uniform over the block
+    uint4 hdr = make_uint4(0xffffffffu, 0u, 0u, 0u);
+    if (use) hdr = *reinterpret_cast<const uint4 *>(a.plan + head);
+    uint32_t recw = (uint32_t)head;   // record of the current chunk (use)
+    uint32_t first_rec = 0xffffffffu, prev_rec = 0xffffffffu;   // thread 0, building
 
     for (int i = tid; i < 12 * K; i += kNT) sm.T[i] = a.T[(int64_t)W.kf0 * 12 + i];
     for (int i = tid; i < K; i += kNT) sm.opt[i] = a.opt_map[W.kf0 + i];
@@ -392,36 +410,76 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
         int tid = threadIdx.x;
         asm volatile("" : "+v"(tid));
         // ---- chunk of whole points: <= CO observations and <= PCAP pairs ------------
-        for (int i = tid; i < Kopt * 8; i += kNT) cm[i] = 0ull;
-        const int cand = p + tid;
-        int P = 0, ps = 0, m = 0, inrange = 0;
-        if (cand < tile.p1) {
-            P = pin.x;
-            ps = pin.w;   // place of the point's first observation
-            m = pin.z;
-            inrange = 1;
+        int q, np;
+        int kp = C::kPiece;   // pairs per piece in this chunk (the same in every thread)
+        uint32_t cw[8];       // use: this thread's words of the chunk's record
+        int npr = 0, nwc = 0, ntot = 0;
+        if (use) {
+            q = (int)hdr.y;
+            npr = (int)(hdr.z & 4095u);
+            nwc = (int)((((hdr.z >> 12) & 1023u) + 2u) >> 1);
+            if (C::kPieceSmall != C::kPiece && ((hdr.z >> 22) & 1u)) kp = C::kPieceSmall;
+            ntot = npr + nwc + ((nblk + 2) >> 1);
+            const uint32_t *src = a.plan + recw + 4;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = tid + kNT * u;
+                cw[u] = i < ntot ? src[i] : 0u;
+            }
+            if (q <= p || q > tile.p1) {   // records that do not fit the tile: not solvable
+                fail = 1;
+                break;
+            }
+            np = q - p;
+            const int base = (int)hdr.w;
+            // the previous chunk's owners read their products from the region that holds
+            // the chunk's ranges
+            __syncthreads();
+            if (tid < np) {
+                pst[tid + 1] = pin.w + pin.z - base;
+                gst[tid] = pin.w;
+                pid[tid] = pin.x;
+                for (int i = pin.w - base; i < pin.w - base + pin.z; ++i) seg[i] = tid;
+            }
+            if (tid == 0) pst[0] = 0;
+            pin = make_int4(0, 0, 0, 0);
+            if (q + tid < tile.p1) pin = a.pinfo[q + tid];
+            if (hdr.x != 0xffffffffu) {
+                recw = hdr.x;
+                hdr = *reinterpret_cast<const uint4 *>(a.plan + recw);
+            }
+        } else {
+            for (int i = tid; i < Kopt * 8; i += kNT) cm[i] = 0ull;
+            const int cand = p + tid;
+            int P = 0, ps = 0, m = 0, inrange = 0;
+            if (cand < tile.p1) {
+                P = pin.x;
+                ps = pin.w;   // place of the point's first observation
+                m = pin.z;
+                inrange = 1;
+            }
+            // observations (high word) and pair slots (low word) up to and including this point
+            const long long incl =
+                block_inclusive_scan64(((long long)m << 32) | (long long)(m * (m + 1) / 2), sm.scan, tid);
+            const int obs_incl = (int)(incl >> 32), pincl = (int)(incl & 0xffffffffll);
+            const int ok = inrange && obs_incl <= C::CO && pincl <= C::PCAP;
+            q = p + __syncthreads_count(ok);
+            if (q == p) {   // one point exceeds a chunk: not solvable here
+                fail = 1;
+                break;
+            }
+            pin = make_int4(0, 0, 0, 0);
+            if (q + tid < tile.p1) pin = a.pinfo[q + tid];
+            // the chunk's point ranges and observation slots go to LDS
+            np = q - p;
+            if (tid < np) {
+                pst[tid + 1] = obs_incl;
+                gst[tid] = ps;
+                pid[tid] = P;
+                for (int i = obs_incl - m; i < obs_incl; ++i) seg[i] = tid;
+            }
+            if (tid == 0) pst[0] = 0;
         }
-        // observations (high word) and pair slots (low word) up to and including this point
-        const long long incl =
-            block_inclusive_scan64(((long long)m << 32) | (long long)(m * (m + 1) / 2), sm.scan, tid);
-        const int obs_incl = (int)(incl >> 32), pincl = (int)(incl & 0xffffffffll);
-        const int ok = inrange && obs_incl <= C::CO && pincl <= C::PCAP;
-        const int q = p + __syncthreads_count(ok);
-        if (q == p) {   // one point exceeds a chunk: not solvable here
-            fail = 1;
-            break;
-        }
-        pin = make_int4(0, 0, 0, 0);
-        if (q + tid < tile.p1) pin = a.pinfo[q + tid];
-        // the chunk's point ranges and observation slots go to LDS
-        const int np = q - p;
-        if (tid < np) {
-            pst[tid + 1] = obs_incl;
-            gst[tid] = ps;
-            pid[tid] = P;
-            for (int i = obs_incl - m; i < obs_incl; ++i) seg[i] = tid;
-        }
-        if (tid == 0) pst[0] = 0;
         int pl = 0, kl = 0, stereo = 0, oct = 0;
         bool act = false;
         double zu = 0, zv = 0, zr = 0;
@@ -469,7 +527,7 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             for (int i = 0; i < 3; ++i) sm.hs[tid * 9 + 6 + i] = bl[i];
             if (!act) ka = -1;
             sm.oka[tid] = ka;
-            if (ka >= 0) {   // the point in its camera's mask; a second hit is a duplicate
+            if (ka >= 0 && !use) {   // the point in its camera's mask; a second hit is a duplicate
                 const unsigned long long bit = 1ull << (pl & 63);
                 dup = (__hip_atomic_fetch_or(&cm[ka * 8 + (pl >> 6)], bit, __ATOMIC_RELAXED,
                                              __HIP_MEMORY_SCOPE_WORKGROUP) & bit) != 0;
@@ -477,10 +535,31 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
         }
         Facc += rho;
         // list counters of phase 3, cleared here so that phases 2 and 3 need no barrier
-        // between them (the previous chunk's last reads of them precede a barrier)
-        for (int B = tid; B < nblk; B += kNT) {
-            sm.cnt[B] = 0;
-            sm.cur[B] = 0;
+        // between them (the previous chunk's last reads of them precede a barrier); a
+        // stored record goes to the lists instead
+        if (!use) {
+            for (int B = tid; B < nblk; B += kNT) {
+                sm.cnt[B] = 0;
+                sm.cur[B] = 0;
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = tid + kNT * u;
+                if (i >= ntot) continue;
+                const uint32_t v = cw[u];
+                if (i < npr) {
+                    sm.pairs[i] = v;
+                } else if (i < npr + nwc) {
+                    const int j = 2 * (i - npr);
+                    pcs[j] = (unsigned short)(v & 0xffffu);
+                    pcs[j + 1] = (unsigned short)(v >> 16);
+                } else {
+                    const int j = 2 * (i - npr - nwc);
+                    pco[j] = (int)(v & 0xffffu);
+                    if (j + 1 <= nblk) pco[j + 1] = (int)(v >> 16);
+                }
+            }
         }
         if (tid < 2 * kGroups) sm.touch[tid] = 0ull;
         const int anydup = __syncthreads_or(dup);
@@ -561,119 +640,154 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
         // camera masks and a pair's place in its block is the number of such points
         // before its own, so the list is ordered by block, then point.  A chunk with a
         // duplicate counts and places its pairs with LDS atomics instead.
-        const int nwrd = (q - p + 63) >> 6;
-        if (!anydup) {
-            for (int B = tid; B < nblk; B += kNT) {
-                const int Bg = bbase + B;
-                const int kA = block_row(Bg, Kopt), kB = kA + (Bg - block_id(kA, kA, Kopt));
-                int c = 0;
-                if (kA != kB)
-                    for (int w = 0; w < nwrd; ++w) c += __popcll(cm[kA * 8 + w] & cm[kB * 8 + w]);
-                sm.cnt[B] = c;
-            }
-        } else if (ka >= 0) {
-            for (int b0 = tid + 1; b0 < s1; b0 += 4) {   // partners four at a time: one wait per four
-                int kb[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) kb[u] = b0 + u < s1 ? sm.oka[b0 + u] : -1;
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    if (kb[u] >= 0) {
-                        const int Bl = (ka <= kb[u] ? block_id(ka, kb[u], Kopt) : block_id(kb[u], ka, Kopt)) - bbase;
-                        if (Bl >= 0 && Bl < nblk) atomicAdd(&sm.cnt[Bl], 1);
-                    }
-            }
-        }
-        __syncthreads();
-        int kp = C::kPiece;   // pairs per piece in this chunk (the same in every thread)
-        if constexpr (C::kPieceSmall != C::kPiece) {
-            // pair offsets (bits 0-11, at most PCAP = 3072), piece offsets for kPieceSmall
-            // (bits 12-21) and for kPiece (bits 22-31) in one scan: a block of c pairs has
-            // at most c / kPiece + 1 pieces, so each piece field stays below
-            // PCAP / kPieceSmall + kPassBlocks = 988 < 1024
-            static_assert(C::PCAP < 4096 && C::PCAP / C::kPieceSmall + kPassBlocks < 1024, "scan fields");
-            const unsigned c = tid < nblk ? (unsigned)sm.cnt[tid] : 0u;
-            const unsigned v = c | (((c + C::kPieceSmall - 1) / C::kPieceSmall) << 12) |
-                               (((c + C::kPiece - 1) / C::kPiece) << 22);
-            unsigned tot;
-            const unsigned incl = block_inclusive_scan_total(v, sm.scan, tid, tot);
-            const bool small = ((tot >> 12) & 1023u) <= (unsigned)C::PB;
-            kp = small ? C::kPieceSmall : C::kPiece;
-            const int sh = small ? 12 : 22;
-            if (tid < nblk) {
-                sm.cnt[tid] = (int)((incl - v) & 4095u);
-                pco[tid] = (int)(((incl - v) >> sh) & 1023u);
-            }
-            if (tid == nblk - 1) {
-                sm.cnt[nblk] = (int)(incl & 4095u);
-                pco[nblk] = (int)((incl >> sh) & 1023u);
-                pcs[(incl >> sh) & 1023u] = (unsigned short)(incl & 4095u);
-            }
-        } else {   // pair offsets (low half) and piece offsets (high half) in one scan
-            const int c = tid < nblk ? sm.cnt[tid] : 0;
-            const int v = c | (((c + C::kPiece - 1) / C::kPiece) << 16);
-            const int incl = block_inclusive_scan(v, sm.scan, tid);
-            if (tid < nblk) {
-                sm.cnt[tid] = (incl - v) & 0xffff;
-                pco[tid] = (incl - v) >> 16;
-            }
-            if (tid == nblk - 1) {
-                sm.cnt[nblk] = incl & 0xffff;
-                pco[nblk] = incl >> 16;
-                if (C::kPiece > 1) pcs[incl >> 16] = (unsigned short)(incl & 0xffff);
-            }
-        }
-        __syncthreads();
-        // Placement.  The pairs of one point are shared round-robin by all its observation
-        // threads (pair g of a point of m observations goes to its thread g mod m), so no
-        // thread places more than ceil((m - 1) / 2) of them; a chunk with a repeated
-        // observation places each observation's pairs with its later partners (atomics).
-        auto place = [&](int sa, int sb, int kA, int kB, int rk, int B) {
-            // first = the observation on the lower camera; flag 2 = two observations of
-            // one point on the same camera
-            const int first = kA <= kB ? sa : sb, second = kA <= kB ? sb : sa;
-            const unsigned fl = kA == kB ? 2u : 0u;
-            const int pos = sm.cnt[B] + rk;
-            sm.pairs[pos] = (unsigned)first | ((unsigned)second << 10) | (fl << 20);
-            if (C::kPiece > 1) {
-                const int pq = kp == C::kPiece ? rk / C::kPiece : rk / C::kPieceSmall;
-                if (rk == pq * kp) pcs[pco[B] + pq] = (unsigned short)pos;
-            }
-        };
-        if (!anydup) {
-            if (has) {
-                const int pw = pl >> 6;
-                const unsigned long long below = (1ull << (pl & 63)) - 1ull;
-                const int mp = s1 - s0, npp = mp * (mp - 1) / 2;
-                for (int g = tid - s0; g < npp; g += mp) {
-                    // pair g = (a, b), a < b, in row order: row a starts at a m - a (a + 1) / 2
-                    const float c = 2.0f * mp - 1.0f;
-                    int ar = (int)((c - sqrtf(fmaxf(c * c - 8.0f * g, 0.0f))) * 0.5f);
-                    ar = min(max(ar, 0), mp - 2);
-                    if (ar > 0 && ar * mp - ar * (ar + 1) / 2 > g) --ar;
-                    if (ar + 1 <= mp - 2 && (ar + 1) * mp - (ar + 1) * (ar + 2) / 2 <= g) ++ar;
-                    const int br = ar + 1 + (g - (ar * mp - ar * (ar + 1) / 2));
-                    const int sa = s0 + ar, sb = s0 + br;
-                    const int kA = sm.oka[sa], kB = sm.oka[sb];
-                    if (kA < 0 || kB < 0) continue;
-                    const int lo = min(kA, kB), hi = max(kA, kB);
-                    const int Bl = block_id(lo, hi, Kopt) - bbase;   // another pass's block
-                    if (Bl < 0 || Bl >= nblk) continue;
-                    int r = __popcll(cm[lo * 8 + pw] & cm[hi * 8 + pw] & below);
-                    for (int w = 0; w < pw; ++w) r += __popcll(cm[lo * 8 + w] & cm[hi * 8 + w]);
-                    place(sa, sb, kA, kB, r, Bl);
+        if (!use) {
+            const int nwrd = (q - p + 63) >> 6;
+            if (!anydup) {
+                for (int B = tid; B < nblk; B += kNT) {
+                    const int Bg = bbase + B;
+                    const int kA = block_row(Bg, Kopt), kB = kA + (Bg - block_id(kA, kA, Kopt));
+                    int c = 0;
+                    if (kA != kB)
+                        for (int w = 0; w < nwrd; ++w) c += __popcll(cm[kA * 8 + w] & cm[kB * 8 + w]);
+                    sm.cnt[B] = c;
+                }
+            } else if (ka >= 0) {
+                for (int b0 = tid + 1; b0 < s1; b0 += 4) {   // partners four at a time: one wait per four
+                    int kb[4];
+    #pragma unroll
+                    for (int u = 0; u < 4; ++u) kb[u] = b0 + u < s1 ? sm.oka[b0 + u] : -1;
+    #pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (kb[u] >= 0) {
+                            const int Bl = (ka <= kb[u] ? block_id(ka, kb[u], Kopt) : block_id(kb[u], ka, Kopt)) - bbase;
+                            if (Bl >= 0 && Bl < nblk) atomicAdd(&sm.cnt[Bl], 1);
+                        }
                 }
             }
-        } else if (ka >= 0) {
-            for (int b = tid + 1; b < s1; ++b) {
-                const int kb = sm.oka[b];
-                if (kb < 0) continue;
-                const int B = block_id(min(ka, kb), max(ka, kb), Kopt) - bbase;
-                if (B < 0 || B >= nblk) continue;
-                place(tid, b, ka, kb, atomicAdd(&sm.cur[B], 1), B);
+            __syncthreads();
+            if constexpr (C::kPieceSmall != C::kPiece) {
+                // pair offsets (bits 0-11, at most PCAP = 3072), piece offsets for kPieceSmall
+                // (bits 12-21) and for kPiece (bits 22-31) in one scan: a block of c pairs has
+                // at most c / kPiece + 1 pieces, so each piece field stays below
+                // PCAP / kPieceSmall + kPassBlocks = 988 < 1024
+                static_assert(C::PCAP < 4096 && C::PCAP / C::kPieceSmall + kPassBlocks < 1024, "scan fields");
+                const unsigned c = tid < nblk ? (unsigned)sm.cnt[tid] : 0u;
+                const unsigned v = c | (((c + C::kPieceSmall - 1) / C::kPieceSmall) << 12) |
+                                   (((c + C::kPiece - 1) / C::kPiece) << 22);
+                unsigned tot;
+                const unsigned incl = block_inclusive_scan_total(v, sm.scan, tid, tot);
+                const bool small = ((tot >> 12) & 1023u) <= (unsigned)C::PB;
+                kp = small ? C::kPieceSmall : C::kPiece;
+                const int sh = small ? 12 : 22;
+                if (tid < nblk) {
+                    sm.cnt[tid] = (int)((incl - v) & 4095u);
+                    pco[tid] = (int)(((incl - v) >> sh) & 1023u);
+                }
+                if (tid == nblk - 1) {
+                    sm.cnt[nblk] = (int)(incl & 4095u);
+                    pco[nblk] = (int)((incl >> sh) & 1023u);
+                    pcs[(incl >> sh) & 1023u] = (unsigned short)(incl & 4095u);
+                }
+            } else {   // pair offsets (low half) and piece offsets (high half) in one scan
+                const int c = tid < nblk ? sm.cnt[tid] : 0;
+                const int v = c | (((c + C::kPiece - 1) / C::kPiece) << 16);
+                const int incl = block_inclusive_scan(v, sm.scan, tid);
+                if (tid < nblk) {
+                    sm.cnt[tid] = (incl - v) & 0xffff;
+                    pco[tid] = (incl - v) >> 16;
+                }
+                if (tid == nblk - 1) {
+                    sm.cnt[nblk] = incl & 0xffff;
+                    pco[nblk] = incl >> 16;
+                    if (C::kPiece > 1) pcs[incl >> 16] = (unsigned short)(incl & 0xffff);
+                }
             }
+            __syncthreads();
+            if (store && tid == 0) {   // room for this chunk's record in the pool
+                const int npr_c = nblk > 0 ? sm.cnt[nblk] : 0, npc_c = nblk > 0 ? pco[nblk] : 0;
+                const unsigned long long words =
+                    (unsigned long long)((4 + npr_c + ((npc_c + 2) >> 1) + ((nblk + 2) >> 1) + 3) & ~3);
+                const unsigned long long off = atomicAdd(a.plan_ctr, words);
+                sm.rec[0] = off + words <= (unsigned long long)a.plan_cap ? (int)off : -1;
+            }
+            // Placement.  The pairs of one point are shared round-robin by all its observation
+            // threads (pair g of a point of m observations goes to its thread g mod m), so no
+            // thread places more than ceil((m - 1) / 2) of them; a chunk with a repeated
+            // observation places each observation's pairs with its later partners (atomics).
+            auto place = [&](int sa, int sb, int kA, int kB, int rk, int B) {
+                // first = the observation on the lower camera; flag 2 = two observations of
+                // one point on the same camera
+                const int first = kA <= kB ? sa : sb, second = kA <= kB ? sb : sa;
+                const unsigned fl = kA == kB ? 2u : 0u;
+                const int pos = sm.cnt[B] + rk;
+                sm.pairs[pos] = (unsigned)first | ((unsigned)second << 10) | (fl << 20);
+                if (C::kPiece > 1) {
+                    const int pq = kp == C::kPiece ? rk / C::kPiece : rk / C::kPieceSmall;
+                    if (rk == pq * kp) pcs[pco[B] + pq] = (unsigned short)pos;
+                }
+            };
+            if (!anydup) {
+                if (has) {
+                    const int pw = pl >> 6;
+                    const unsigned long long below = (1ull << (pl & 63)) - 1ull;
+                    const int mp = s1 - s0, npp = mp * (mp - 1) / 2;
+                    for (int g = tid - s0; g < npp; g += mp) {
+                        // pair g = (a, b), a < b, in row order: row a starts at a m - a (a + 1) / 2
+                        const float c = 2.0f * mp - 1.0f;
+                        int ar = (int)((c - sqrtf(fmaxf(c * c - 8.0f * g, 0.0f))) * 0.5f);
+                        ar = min(max(ar, 0), mp - 2);
+                        if (ar > 0 && ar * mp - ar * (ar + 1) / 2 > g) --ar;
+                        if (ar + 1 <= mp - 2 && (ar + 1) * mp - (ar + 1) * (ar + 2) / 2 <= g) ++ar;
+                        const int br = ar + 1 + (g - (ar * mp - ar * (ar + 1) / 2));
+                        const int sa = s0 + ar, sb = s0 + br;
+                        const int kA = sm.oka[sa], kB = sm.oka[sb];
+                        if (kA < 0 || kB < 0) continue;
+                        const int lo = min(kA, kB), hi = max(kA, kB);
+                        const int Bl = block_id(lo, hi, Kopt) - bbase;   // another pass's block
+                        if (Bl < 0 || Bl >= nblk) continue;
+                        int r = __popcll(cm[lo * 8 + pw] & cm[hi * 8 + pw] & below);
+                        for (int w = 0; w < pw; ++w) r += __popcll(cm[lo * 8 + w] & cm[hi * 8 + w]);
+                        place(sa, sb, kA, kB, r, Bl);
+                    }
+                }
+            } else if (ka >= 0) {
+                for (int b = tid + 1; b < s1; ++b) {
+                    const int kb = sm.oka[b];
+                    if (kb < 0) continue;
+                    const int B = block_id(min(ka, kb), max(ka, kb), Kopt) - bbase;
+                    if (B < 0 || B >= nblk) continue;
+                    place(tid, b, ka, kb, atomicAdd(&sm.cur[B], 1), B);
+                }
+            }
+            __syncthreads();
+            if (store) {   // the chunk's record, for the later launches of this round
+                const int off = sm.rec[0];
+                if (off < 0) {
+                    store = false;
+                } else {
+                    const int npr_c = nblk > 0 ? sm.cnt[nblk] : 0, npc_c = nblk > 0 ? pco[nblk] : 0;
+                    const int nwc_c = (npc_c + 2) >> 1, nwo_c = (nblk + 2) >> 1;
+                    uint32_t *dst = a.plan + off;
+                    for (int i = tid; i < npr_c; i += kNT) dst[4 + i] = sm.pairs[i];
+                    for (int i = tid; i < nwc_c; i += kNT)
+                        dst[4 + npr_c + i] = (uint32_t)pcs[2 * i] | ((uint32_t)pcs[2 * i + 1] << 16);
+                    for (int i = tid; i < nwo_c; i += kNT)
+                        dst[4 + npr_c + nwc_c + i] =
+                            (uint32_t)pco[2 * i] | ((2 * i + 1 <= nblk ? (uint32_t)pco[2 * i + 1] : 0u) << 16);
+                    if (tid == 0) {
+                        const uint32_t sm_flag = (C::kPieceSmall != C::kPiece && kp == C::kPieceSmall) ? 1u : 0u;
+                        *reinterpret_cast<uint4 *>(dst) =
+                            make_uint4(0xffffffffu, (uint32_t)q, (uint32_t)npr_c | ((uint32_t)npc_c << 12) | (sm_flag << 22),
+                                       (uint32_t)gst[0]);
+                        if (prev_rec != 0xffffffffu) a.plan[prev_rec] = (uint32_t)off;
+                        else first_rec = (uint32_t)off;
+                        prev_rec = (uint32_t)off;
+                    }
+                }
+            }
+        } else {
+            __syncthreads();   // Z staged
         }
-        __syncthreads();
 
         // ---- 4. piece products, PB at a time, then each owner sums its rows --------------
         const int npieces = nblk > 0 ? pco[nblk] : 0;
@@ -766,6 +880,8 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
         a.partd[4 * t + 2] = anyfail ? 1.0 : 0.0;
         a.partd[4 * t + 3] = 0.0;
     }
+    // every chunk of the tile has its record: the later launches of the round use them
+    if (tid == 0 && store && !anyfail && first_rec != 0xffffffffu) a.plan_head[slot] = (int32_t)first_rec;
     (void)E;
 }
 
@@ -783,6 +899,18 @@ hipError_t launch_linearize(const LinArgs &a, int ntiles, int passes, size_t lds
         if (zf) hipLaunchKernelGGL((k_linearize<double, float, double>), grid, block, lds, s, a);
         else hipLaunchKernelGGL((k_linearize<double, double, double>), grid, block, lds, s, a);
     }
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_plan_reset(int32_t *head, int n, unsigned long long *ctr) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) head[i] = -1;
+    if (i == 0) *ctr = 0ull;
+}
+
+hipError_t launch_plan_reset(const LinArgs &a, int slots, hipStream_t s) {
+    if (!a.plan_head || slots <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_plan_reset, dim3((slots + 255) / 256), dim3(256), 0, s, a.plan_head, slots, a.plan_ctr);
     return hipGetLastError();
 }
 

@@ -99,7 +99,9 @@ struct Plan {
     // workspace byte offsets
     size_t o_win, o_tiles, o_order, o_opt, o_kfoff, o_ptoff, o_obsoff, o_upload_end;
     size_t o_ptstart, o_ctl, o_T, o_X0, o_X1, o_part, o_partr, o_partd, o_partu, o_red, o_fact, o_redflag, o_dp, o_pf,
-        o_pkey, o_ptmp, o_pinfo, o_skf, o_stype, o_soct, o_sz, o_smask, o_stats, o_err, o_log, total;
+        o_pkey, o_ptmp, o_pinfo, o_skf, o_stype, o_soct, o_sz, o_smask, o_stats, o_err, o_log, o_planhead, o_planctr,
+        o_plan, total;
+    int64_t plan_cap = 0;   // words of the pool of chunk records (0: rebuilt at every step)
     int log_cap = 0;
     // stereo-inertial solve
     bool vi = false;
@@ -401,6 +403,18 @@ lba_status build_plan(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, Pl
         return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "trial_log must be in [0, 4096]");
     pl.log_cap = opt.trial_log;
     pl.o_log = o;     o = align256(o + sizeof(TrialRec) * (size_t)pl.log_cap * nw);
+    // chunk records of the linearisation (kept for the rest of an LM round): about 3 words
+    // per observation on the batched workload (pairs, piece starts) plus up to 243 per
+    // chunk (header, piece offsets of the blocks); the pool is sized at 8 per observation
+    // plus 256 per 256 observations and per tile and pass.  A tile whose records do not
+    // fit forms them at every step instead.
+    if (opt.pair_cache != 0 && opt.pair_cache != 1)
+        return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "pair_cache must be 0 or 1");
+    const int64_t slots = (int64_t)std::max<size_t>(pl.tiles.size(), 1) * pl.lin_passes;
+    pl.plan_cap = opt.pair_cache ? 8 * (int64_t)P->n_obs + 256 * ((int64_t)P->n_obs / 256 + slots) : 0;
+    pl.o_planhead = o; o = align256(o + sizeof(int32_t) * slots);
+    pl.o_planctr = o;  o = align256(o + sizeof(unsigned long long));
+    pl.o_plan = o;     o = align256(o + sizeof(uint32_t) * (size_t)pl.plan_cap);
     if (pl.vi) {
         pl.o_vred = o;  o = align256(o + sizeof(double) * std::max<int64_t>(vred, 1));
         pl.o_vdp = o;   o = align256(o + sizeof(double) * std::max<int64_t>(vdp, 1));
@@ -772,6 +786,12 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
     la.waves = pl.waves;
     la.acc32 = (pl.mixed && opt.schur_fp32_accum) ? 1 : 0;
     la.self_copies = pl.lin_copies;
+    if (pl.plan_cap > 0) {
+        la.plan = static_cast<uint32_t *>(W_(pl.o_plan));
+        la.plan_ctr = static_cast<unsigned long long *>(W_(pl.o_planctr));
+        la.plan_head = static_cast<int32_t *>(W_(pl.o_planhead));
+        la.plan_cap = pl.plan_cap;
+    }
     la.c = c;
 
     ReduceArgs ra;
@@ -874,7 +894,11 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
         ua.robust = robust;
         da.round = round;
         ia.round = round;
-        HIPCHK(timed(ctx, LBA_KCLASS_LINEARIZE_INIT, s, [&] { return launch_init(la, ntiles, pl.init_lds, s); }));
+        // the active observations change between rounds: the chunk records are formed again
+        HIPCHK(timed(ctx, LBA_KCLASS_LINEARIZE_INIT, s, [&] {
+            hipError_t e = launch_plan_reset(la, ntiles * pl.lin_passes, s);
+            return e != hipSuccess ? e : launch_init(la, ntiles, pl.init_lds, s);
+        }));
         if (pl.vi) HIPCHK(timed(ctx, LBA_KCLASS_INERTIAL, s, [&] { return launch_vi_eval(va, s); }));
         HIPCHK(timed(ctx, LBA_KCLASS_INIT_REDUCE, s, [&] { return launch_init_reduce(ia, nw, s); }));
         int steps_done = 0;
@@ -1207,6 +1231,7 @@ void lba_default_options(lba_options *o) {
     o->tau = 1e-5;
     o->points_per_tile = 0;
     o->use_graphs = 1;
+    o->pair_cache = 1;
 }
 
 lba_status lba_create(const lba_options *opt, int32_t device, lba_ctx **out) {

@@ -103,6 +103,15 @@ struct LinArgs {
     int acc32;                   // mixed precision: sum S and the self terms in FP32
     int self_copies;             // copies of the camera sums of the self terms: one per
                                  // wavefront (bitwise-repeatable sums), or 1
+    // chunk records of the pair structure, kept for the rest of an LM round (the pairs of
+    // a chunk depend only on which observations are active, which changes only between
+    // rounds): a pool of 32-bit words, its size in words and its fill counter, and per
+    // tile and pass the word offset of the first record (-1: none, built by the next
+    // launch).  plan_head == nullptr: the structure is rebuilt at every step.
+    uint32_t *plan;
+    unsigned long long *plan_ctr;
+    int32_t *plan_head;
+    int64_t plan_cap;
     SolveConsts c;
 };
 
@@ -306,6 +315,7 @@ hipError_t launch_vi_split(const ViArgs &a, int n_windows, hipStream_t s);
 hipError_t launch_vi_finish(const ViArgs &a, hipStream_t s);
 
 hipError_t launch_linearize(const LinArgs &a, int ntiles, int passes, size_t lds, bool mixed, hipStream_t s);
+hipError_t launch_plan_reset(const LinArgs &a, int slots, hipStream_t s);   // forget the chunk records
 int lin_passes(int kopt);   // passes over the camera blocks of a window with kopt optimisable keyframes
 hipError_t launch_update(const UpdArgs &a, int ntiles, size_t lds, bool mixed, hipStream_t s);
 hipError_t launch_init(const LinArgs &a, int ntiles, size_t lds, hipStream_t s);

@@ -43,7 +43,7 @@ class Options(C.Structure):
                 ("huber2_mono", C.c_double), ("huber2_stereo", C.c_double),
                 ("chi2_mono", C.c_double), ("chi2_stereo", C.c_double), ("tau", C.c_double),
                 ("points_per_tile", C.c_int32), ("use_graphs", C.c_int32), ("trial_log", C.c_int32),
-                ("schur_fp32_accum", C.c_int32)]
+                ("schur_fp32_accum", C.c_int32), ("pair_cache", C.c_int32)]
 
 
 class Intrinsics(C.Structure):

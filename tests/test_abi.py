@@ -24,7 +24,7 @@ def test_library_exports_every_declared_symbol():
     for name in _declared():
         assert hasattr(L, name), f"{name} declared in lba.h but not exported"
     assert set(_declared()) <= set(lba.EXPORTS)
-    assert L.lba_abi_version() == 3
+    assert L.lba_abi_version() == 4
     assert L.lba_status_string(-5).decode() == "unsupported problem size"
 
 
@@ -34,14 +34,14 @@ def test_default_options_match_the_documented_values():
     assert (o.iters_round1, o.iters_round2, o.max_trials, o.round2_robust) == (5, 10, 10, 1)
     assert (o.huber2_mono, o.huber2_stereo, o.chi2_mono, o.chi2_stereo) == (5.991, 7.815, 5.991, 7.815)
     assert o.tau == 1e-5 and o.precision == lba.PREC_FP64
-    assert o.trial_log == 0 and o.use_graphs == 1 and o.schur_fp32_accum == 0
+    assert o.trial_log == 0 and o.use_graphs == 1 and o.schur_fp32_accum == 0 and o.pair_cache == 1
 
 
 def test_struct_layouts_match_the_header():
     """The ctypes mirrors have the sizes of the C structs (x86-64 System V layout)."""
     import ctypes as C
     from paper_2511_02036_amd import lba
-    assert C.sizeof(lba.Options) == 6 * 4 + 5 * 8 + 4 * 4
+    assert C.sizeof(lba.Options) == 6 * 4 + 5 * 8 + 5 * 4 + 4   # tail padding to 8 bytes
     assert C.sizeof(lba.TrialRecord) == 6 * 4 + 4 * 8
     assert C.sizeof(lba.Result) == 5 * 8
 
