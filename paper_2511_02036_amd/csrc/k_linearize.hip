@@ -72,7 +72,8 @@ struct LinCfg {
 
 template <typename Real>
 struct LinSmem {
-    double *T;       // K x 12 poses
+    double *T;       // K x 12 poses, then 34 weights: 1 / sigma2 per octave (32), Huber
+                     // thresholds mono, stereo
     int *opt;        // K
     Real *Z;         // CO x ZS (18 values per observation)
     double *hs;      // CO x 9    FP64 Hll_a (6) and bl_a (3) for the point sums
@@ -89,8 +90,8 @@ struct LinSmem {
     int *scan;       // 16: per-wavefront totals
     unsigned long long *touch;   // 2 x kGroups: per group, blocks with pairs in the batch, then
                                  // Kopt x 8: per camera, bit mask of the chunk's points it observes
-    double *red;     // 8 x 2
-    int *rec;        // 4: word offset of the chunk's record in the pool (-1: not stored)
+    double *red;     // 8 x 2, then 4 ints: word offset of the chunk's record in the pool
+                     // (-1: not stored)
 };
 
 // value of the neighbouring lane: lanes 2k and 2k + 1 exchange (DPP quad permutation
@@ -199,7 +200,7 @@ __host__ __device__ inline size_t lin_carve(unsigned char *base, int K, int Kopt
     using C = LinCfg<Real>;
     size_t o = 0;
     auto take = [&](size_t bytes) { void *p = base ? (void *)(base + o) : nullptr; o = align_up(o + bytes, 16); return p; };
-    void *T = take(sizeof(double) * 12 * K);
+    void *T = take(sizeof(double) * (12 * K + kMaxLevels + 2));
     void *opt = take(sizeof(int) * K);
     void *Z = take(sizeof(Real) * C::CO * C::ZS);
     // the staging of phases 1-2 (point-sum terms, then the chunk's observation ranges
@@ -220,14 +221,13 @@ __host__ __device__ inline size_t lin_carve(unsigned char *base, int K, int Kopt
     void *touch = take(sizeof(unsigned long long) * (2 * kGroups + 8 * (Kopt > 0 ? Kopt : 1)));
     void *oka = take(sizeof(int) * C::CO);
     void *scan = take(sizeof(int) * 16);
-    void *red = take(sizeof(double) * 2 * (kNT / 64));
+    void *red = take(sizeof(double) * 2 * (kNT / 64) + sizeof(int) * 4);
     void *dacc = take(sizeof(double) * copies * Kopt * 27);
-    void *rec = take(sizeof(int) * 4);
     if (s) {
         s->T = (double *)T; s->opt = (int *)opt; s->Z = (Real *)Z; s->hs = (double *)hs; s->ints = (int *)ints;
         s->dacc = (double *)dacc; s->pairs = (unsigned *)pairs; s->pcs = (unsigned short *)pcs; s->prod = (Real *)prod;
         s->cnt = (int *)cnt; s->cur = (int *)cur; s->touch = (unsigned long long *)touch; s->oka = (int *)oka;
-        s->scan = (int *)scan; s->red = (double *)red; s->rec = (int *)rec;
+        s->scan = (int *)scan; s->red = (double *)red;
     }
     return o;
 }
@@ -340,6 +340,8 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
     LinSmem<Real> sm;
     lin_carve<Real>(smem, K, Kopt, a.self_copies, &sm);
     unsigned long long *const cm = sm.touch + 2 * kGroups;
+    double *const wt = sm.T + 12 * K;                                   // weights
+    int *const rec = reinterpret_cast<int *>(sm.red + 2 * (kNT / 64));  // record offset
     int *const pst = sm.ints;                           // chunk-local observation starts
     int *const gst = pst + kNT + 1;                     // place of each point's first observation
     int *const pid = gst + kNT;                         // global index of each point
@@ -359,7 +361,7 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
     // blocks' piece offsets (16-bit).
     const int slot = t * (int)gridDim.y + (int)blockIdx.y;
     const int head = a.plan_head ? a.plan_head[slot] : -1;
-    const bool use = head >= 0;
+    const bool use = head >= 0 && (int64_t)head + 4 <= a.plan_cap;
     bool store = !use && a.plan_head != nullptr;   // uniform over the block
     uint4 hdr = make_uint4(0xffffffffu, 0u, 0u, 0u);
     if (use) hdr = *reinterpret_cast<const uint4 *>(a.plan + head);
@@ -368,6 +370,9 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
 
     for (int i = tid; i < 12 * K; i += kNT) sm.T[i] = a.T[(int64_t)W.kf0 * 12 + i];
     for (int i = tid; i < K; i += kNT) sm.opt[i] = a.opt_map[W.kf0 + i];
+    // the weights by octave and type, read per observation: from LDS rather than from the
+    // kernel arguments (one dependent memory round trip less per chunk)
+    if (tid < kMaxLevels + 2) wt[tid] = tid < kMaxLevels ? a.c.inv_sigma2[tid] : a.c.huber2[tid - kMaxLevels];
 
     // ---- owned entries: thread g * 36 + q (g < 14) owns entry q = 6 i + j of the 6 x 6
     // blocks bbase + g + 14 k (kA <= kB).  In a diagonal block the entries j <= i are S, the
@@ -420,13 +425,14 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             nwc = (int)((((hdr.z >> 12) & 1023u) + 2u) >> 1);
             if (C::kPieceSmall != C::kPiece && ((hdr.z >> 22) & 1u)) kp = C::kPieceSmall;
             ntot = npr + nwc + ((nblk + 2) >> 1);
+            if ((int64_t)recw + 4 + ntot > a.plan_cap) ntot = 0;   // (the pool's bound; fails below)
             const uint32_t *src = a.plan + recw + 4;
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int i = tid + kNT * u;
                 cw[u] = i < ntot ? src[i] : 0u;
             }
-            if (q <= p || q > tile.p1) {   // records that do not fit the tile: not solvable
+            if (q <= p || q > tile.p1 || ntot == 0) {   // records that do not fit the tile: not solvable
                 fail = 1;
                 break;
             }
@@ -444,7 +450,7 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             if (tid == 0) pst[0] = 0;
             pin = make_int4(0, 0, 0, 0);
             if (q + tid < tile.p1) pin = a.pinfo[q + tid];
-            if (hdr.x != 0xffffffffu) {
+            if (hdr.x != 0xffffffffu && (int64_t)hdr.x + 4 <= a.plan_cap) {
                 recw = hdr.x;
                 hdr = *reinterpret_cast<const uint4 *>(a.plan + recw);
             }
@@ -495,7 +501,10 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             X1 = Xs[3 * Pg + 1];
             X2 = Xs[3 * Pg + 2];
             kl = a.sobs.kf[o];
-            act = !a.smask || !a.smask[o];
+            // the flag is loaded without a branch (from a readable byte array when there
+            // is none), so that it issues with the other loads
+            const uint8_t flag = (a.smask ? a.smask : a.sobs.type)[o];
+            act = (a.smask == nullptr) | (flag == 0);
             stereo = a.sobs.type[o];
             oct = a.sobs.oct[o];
             load_z<ZT>(a.sobs, o, zu, zv, zr);
@@ -514,9 +523,9 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             const double *T = sm.T + kl * 12;
             double xc, yc, zc, eu, ev, er;
             const double e2 = residual(cam, T, X0, X1, X2, zu, zv, zr, stereo, xc, yc, zc, eu, ev, er);
-            const double isg = a.c.inv_sigma2[oct];
+            const double isg = wt[oct];
             double w;
-            huber(e2 * isg, a.c.huber2[stereo], a.robust, rho, w);
+            huber(e2 * isg, wt[kMaxLevels + stereo], a.robust, rho, w);
             if (!act) rho = 0.0;
             omd = act ? w * isg : 0.0;
             double Hll[6], bl[3];
@@ -708,7 +717,7 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
                 const unsigned long long words =
                     (unsigned long long)((4 + npr_c + ((npc_c + 2) >> 1) + ((nblk + 2) >> 1) + 3) & ~3);
                 const unsigned long long off = atomicAdd(a.plan_ctr, words);
-                sm.rec[0] = off + words <= (unsigned long long)a.plan_cap ? (int)off : -1;
+                rec[0] = off + words <= (unsigned long long)a.plan_cap ? (int)off : -1;
             }
             // Placement.  The pairs of one point are shared round-robin by all its observation
             // threads (pair g of a point of m observations goes to its thread g mod m), so no
@@ -761,7 +770,7 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             }
             __syncthreads();
             if (store) {   // the chunk's record, for the later launches of this round
-                const int off = sm.rec[0];
+                const int off = rec[0];
                 if (off < 0) {
                     store = false;
                 } else {

@@ -23,6 +23,7 @@ template <typename Real>
 struct UpdSmem {
     double *T;      // K x 12 current poses
     double *Tn;     // K x 12 trial poses
+    double *wt;     // 34: 1 / sigma2 per octave (32), Huber thresholds mono, stereo
     int *opt;       // K
     double *dp;     // n
     double *stgd;   // waves x 64 x 3: q_a
@@ -36,6 +37,7 @@ static size_t upd_lds_t(int K, int n, int waves, size_t real) {
     size_t o = 0;
     o = align_up_u(o + sizeof(double) * 12 * K, 16);
     o = align_up_u(o + sizeof(double) * 12 * K, 16);
+    o = align_up_u(o + sizeof(double) * (kMaxLevels + 2), 16);
     o = align_up_u(o + sizeof(int) * K, 16);
     o = align_up_u(o + sizeof(double) * (n > 0 ? n : 1), 16);
     o = align_up_u(o + sizeof(double) * waves * 64 * 3, 16);
@@ -59,6 +61,8 @@ __device__ inline UpdSmem<Real> carve_upd(unsigned char *base, int K, int n, int
     o = align_up_u(o + sizeof(double) * 12 * K, 16);
     s.Tn = reinterpret_cast<double *>(base + o);
     o = align_up_u(o + sizeof(double) * 12 * K, 16);
+    s.wt = reinterpret_cast<double *>(base + o);
+    o = align_up_u(o + sizeof(double) * (kMaxLevels + 2), 16);
     s.opt = reinterpret_cast<int *>(base + o);
     o = align_up_u(o + sizeof(int) * K, 16);
     s.dp = reinterpret_cast<double *>(base + o);
@@ -95,6 +99,10 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(UpdArgs a) {
     for (int i = threadIdx.x; i < 12 * K; i += blockDim.x) sm.T[i] = a.T[(int64_t)W.kf0 * 12 + i];
     for (int i = threadIdx.x; i < K; i += blockDim.x) sm.opt[i] = a.opt_map[W.kf0 + i];
     for (int i = threadIdx.x; i < n; i += blockDim.x) sm.dp[i] = dpw[i];
+    // the weights by octave and type, read per observation: from LDS rather than from the
+    // kernel arguments (one dependent memory round trip less per chunk)
+    if (threadIdx.x < kMaxLevels + 2)
+        sm.wt[threadIdx.x] = threadIdx.x < kMaxLevels ? a.c.inv_sigma2[threadIdx.x] : a.c.huber2[threadIdx.x - kMaxLevels];
     __syncthreads();
     for (int k = threadIdx.x; k < K; k += blockDim.x) {
         const int ok = sm.opt[k];
@@ -156,7 +164,10 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(UpdArgs a) {
         if (o < a.obs.n_obs) {
             jl = a.obs.pt[o];
             kl = a.obs.kf[o];
-            act = !a.mask || !a.mask[o];
+            // the flag is loaded without a branch (from a readable byte array when there
+            // is none), so that it issues with the other loads
+            const uint8_t flag = (a.mask ? a.mask : a.obs.type)[o];
+            act = (a.mask == nullptr) | (flag == 0);
             stereo = a.obs.type[o];
             oct = a.obs.oct[o];
             load_z<ZT>(a.obs, o, zu, zv, zr);
@@ -180,9 +191,9 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(UpdArgs a) {
                 const double *T = sm.T + kl * 12;
                 double xc, yc, zc, eu, ev, er;
                 const double e2 = residual(cam, T, X0, X1, X2, zu, zv, zr, stereo, xc, yc, zc, eu, ev, er);
-                const double isg = a.c.inv_sigma2[oct];
+                const double isg = sm.wt[oct];
                 double rho, w;
-                huber(e2 * isg, a.c.huber2[stereo], a.robust, rho, w);
+                huber(e2 * isg, sm.wt[kMaxLevels + stereo], a.robust, rho, w);
                 const double *d = sm.dp + 6 * ka;
                 obs_step_q(cam, T, xc, yc, zc, stereo, w * isg, d[1] * zc - d[2] * yc + d[3],
                            d[2] * xc - d[0] * zc + d[4], d[0] * yc - d[1] * xc + d[5], qv);
@@ -237,7 +248,7 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(UpdArgs a) {
             double xc, yc, zc, eu, ev, er;
             const double e2 = residual(cam, sm.Tn + kl * 12, Y0, Y1, Y2, zu, zv, zr, stereo, xc, yc, zc, eu, ev, er);
             double rho, w;
-            huber(e2 * a.c.inv_sigma2[oct], a.c.huber2[stereo], a.robust, rho, w);
+            huber(e2 * sm.wt[oct], sm.wt[kMaxLevels + stereo], a.robust, rho, w);
             Ftr += rho;
         }
         wave_sync();

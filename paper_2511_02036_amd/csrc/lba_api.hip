@@ -410,8 +410,11 @@ lba_status build_plan(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, Pl
     // fit forms them at every step instead.
     if (opt.pair_cache != 0 && opt.pair_cache != 1)
         return set_error(ctx, LBA_ERR_INVALID_ARGUMENT, "pair_cache must be 0 or 1");
-    const int64_t slots = (int64_t)std::max<size_t>(pl.tiles.size(), 1) * pl.lin_passes;
+    // one slot per block of the linearisation's grid (tiles x passes; a batch without
+    // optimisable keyframes has no pass but still launches one row of blocks)
+    const int64_t slots = (int64_t)std::max<size_t>(pl.tiles.size(), 1) * std::max(pl.lin_passes, 1);
     pl.plan_cap = opt.pair_cache ? 8 * (int64_t)P->n_obs + 256 * ((int64_t)P->n_obs / 256 + slots) : 0;
+    pl.plan_cap = std::min<int64_t>(pl.plan_cap, INT32_MAX - 4);   // word offsets are 32-bit
     pl.o_planhead = o; o = align256(o + sizeof(int32_t) * slots);
     pl.o_planctr = o;  o = align256(o + sizeof(unsigned long long));
     pl.o_plan = o;     o = align256(o + sizeof(uint32_t) * (size_t)pl.plan_cap);
@@ -896,7 +899,7 @@ lba_status solve_impl(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, lb
         ia.round = round;
         // the active observations change between rounds: the chunk records are formed again
         HIPCHK(timed(ctx, LBA_KCLASS_LINEARIZE_INIT, s, [&] {
-            hipError_t e = launch_plan_reset(la, ntiles * pl.lin_passes, s);
+            hipError_t e = launch_plan_reset(la, ntiles * std::max(pl.lin_passes, 1), s);
             return e != hipSuccess ? e : launch_init(la, ntiles, pl.init_lds, s);
         }));
         if (pl.vi) HIPCHK(timed(ctx, LBA_KCLASS_INERTIAL, s, [&] { return launch_vi_eval(va, s); }));
