@@ -408,6 +408,32 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
     // the point records of the next chunk are loaded one chunk ahead (thread t: point p + t)
     int4 pin = make_int4(0, 0, 0, 0);
     if (tile.p0 + tid < tile.p1) pin = a.pinfo[tile.p0 + tid];
+    // With stored records the next chunk's first place is known one chunk ahead, so (in
+    // FP32 arithmetic, whose registers allow it) the next chunk's observations (by place:
+    // slot s holds place base + s) and its points' positions are loaded during the current
+    // chunk's products, and its first phase waits on no memory.
+    constexpr bool kPre = sizeof(Real) == 4;
+    bool nxt = false;   // use: a next chunk exists (its header is in hdr)
+    bool pre = false;   // this chunk's observations and positions are in the registers below
+    // (each loaded value stays in its own register until the next chunk uses it: combining
+    // them here would wait on the loads)
+    int pf_kf = 0, pf_type = 0, pf_oct = 0, pf_flag = 0;
+    ZT pf_z0 = 0, pf_z1 = 0, pf_z2 = 0;
+    double pf_X0 = 0, pf_X1 = 0, pf_X2 = 0;   // thread t: position of the chunk's point t
+    uint32_t cw[8];   // use: this thread's words of the chunk's record (loaded with the above)
+    // the record words of the chunk whose header is in hdr and which starts at word recw
+    auto load_words = [&](int tid_) {
+        const int npr_ = (int)(hdr.z & 4095u);
+        const int nwc_ = (int)((((hdr.z >> 12) & 1023u) + 2u) >> 1);
+        int ntot_ = npr_ + nwc_ + ((nblk + 2) >> 1);
+        if ((int64_t)recw + 4 + ntot_ > a.plan_cap) ntot_ = 0;
+        const uint32_t *src = a.plan + recw + 4;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = tid_ + kNT * u;
+            cw[u] = i < ntot_ ? src[i] : 0u;
+        }
+    };
     for (int p = tile.p0; p < tile.p1;) {
         // The thread index is re-derived per chunk behind an empty asm statement, so the
         // compiler recomputes the LDS addresses built from it inside the chunk instead of
@@ -417,7 +443,6 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
         // ---- chunk of whole points: <= CO observations and <= PCAP pairs ------------
         int q, np;
         int kp = C::kPiece;   // pairs per piece in this chunk (the same in every thread)
-        uint32_t cw[8];       // use: this thread's words of the chunk's record
         int npr = 0, nwc = 0, ntot = 0;
         if (use) {
             q = (int)hdr.y;
@@ -426,12 +451,7 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             if (C::kPieceSmall != C::kPiece && ((hdr.z >> 22) & 1u)) kp = C::kPieceSmall;
             ntot = npr + nwc + ((nblk + 2) >> 1);
             if ((int64_t)recw + 4 + ntot > a.plan_cap) ntot = 0;   // (the pool's bound; fails below)
-            const uint32_t *src = a.plan + recw + 4;
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int i = tid + kNT * u;
-                cw[u] = i < ntot ? src[i] : 0u;
-            }
+            if (!(kPre && pre)) load_words(tid);
             if (q <= p || q > tile.p1 || ntot == 0) {   // records that do not fit the tile: not solvable
                 fail = 1;
                 break;
@@ -439,8 +459,15 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             np = q - p;
             const int base = (int)hdr.w;
             // the previous chunk's owners read their products from the region that holds
-            // the chunk's ranges
+            // the chunk's ranges (and its products read Z, which holds the positions until
+            // phase 2)
             __syncthreads();
+            if (kPre && pre && tid < np) {
+                double *const xs = reinterpret_cast<double *>(sm.Z);
+                xs[3 * tid] = pf_X0;
+                xs[3 * tid + 1] = pf_X1;
+                xs[3 * tid + 2] = pf_X2;
+            }
             if (tid < np) {
                 pst[tid + 1] = pin.w + pin.z - base;
                 gst[tid] = pin.w;
@@ -450,7 +477,8 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             if (tid == 0) pst[0] = 0;
             pin = make_int4(0, 0, 0, 0);
             if (q + tid < tile.p1) pin = a.pinfo[q + tid];
-            if (hdr.x != 0xffffffffu && (int64_t)hdr.x + 4 <= a.plan_cap) {
+            nxt = hdr.x != 0xffffffffu && (int64_t)hdr.x + 4 <= a.plan_cap;
+            if (nxt) {
                 recw = hdr.x;
                 hdr = *reinterpret_cast<const uint4 *>(a.plan + recw);
             }
@@ -495,19 +523,33 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
         if (has) {   // observation slot tid: observation tid - pst[pl] of chunk point pl, and
                      // its point's position, loaded together
             pl = seg[tid];
-            const int o = gst[pl] + tid - pst[pl];   // the chunk's places are contiguous
-            const int64_t Pg = pid[pl];
-            X0 = Xs[3 * Pg];
-            X1 = Xs[3 * Pg + 1];
-            X2 = Xs[3 * Pg + 2];
-            kl = a.sobs.kf[o];
-            // the flag is loaded without a branch (from a readable byte array when there
-            // is none), so that it issues with the other loads
-            const uint8_t flag = (a.smask ? a.smask : a.sobs.type)[o];
-            act = (a.smask == nullptr) | (flag == 0);
-            stereo = a.sobs.type[o];
-            oct = a.sobs.oct[o];
-            load_z<ZT>(a.sobs, o, zu, zv, zr);
+            if (kPre && pre) {
+                const double *const xs = reinterpret_cast<const double *>(sm.Z);
+                X0 = xs[3 * pl];
+                X1 = xs[3 * pl + 1];
+                X2 = xs[3 * pl + 2];
+                kl = pf_kf;
+                stereo = pf_type;
+                oct = pf_oct;
+                act = (a.smask == nullptr) | (pf_flag == 0);
+                zu = (double)pf_z0;
+                zv = (double)pf_z1;
+                zr = (double)pf_z2;
+            } else {
+                const int o = gst[pl] + tid - pst[pl];   // the chunk's places are contiguous
+                const int64_t Pg = pid[pl];
+                X0 = Xs[3 * Pg];
+                X1 = Xs[3 * Pg + 1];
+                X2 = Xs[3 * Pg + 2];
+                kl = a.sobs.kf[o];
+                // the flag is loaded without a branch (from a readable byte array when
+                // there is none), so that it issues with the other loads
+                const uint8_t flag = (a.smask ? a.smask : a.sobs.type)[o];
+                act = (a.smask == nullptr) | (flag == 0);
+                stereo = a.sobs.type[o];
+                oct = a.sobs.oct[o];
+                load_z<ZT>(a.sobs, o, zu, zv, zr);
+            }
         }
 
         // ---- 1. per-observation terms -------------------------------------------------
@@ -571,17 +613,33 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             }
         }
         if (tid < 2 * kGroups) sm.touch[tid] = 0ull;
-        const int anydup = __syncthreads_or(dup);
+        int anydup = 0;   // a chunk with stored records was formed without duplicates
+        if (use) __syncthreads();
+        else anydup = __syncthreads_or(dup);
 
         // ---- 2. per-point sums, point factor, staged Z_a, D_a, r_a ---------------------
         double V[6] = {0, 0, 0, 0, 0, 0};
         double bs[3] = {0, 0, 0};
-        if (has) {
-            for (int m = s0; m < s1; ++m) {
+        if (has) {   // two observations per step: their 18 loads issue together
+            for (int m = s0; m < s1; m += 2) {
+                const bool two = m + 1 < s1;
+                const double *h0 = sm.hs + m * 9, *h1 = sm.hs + (two ? m + 1 : m) * 9;
+                double u0[9], u1[9];
 #pragma unroll
-                for (int i = 0; i < 6; ++i) V[i] += sm.hs[m * 9 + i];
+                for (int i = 0; i < 9; ++i) {
+                    u0[i] = h0[i];
+                    u1[i] = h1[i];
+                }
 #pragma unroll
-                for (int i = 0; i < 3; ++i) bs[i] += sm.hs[m * 9 + 6 + i];
+                for (int i = 0; i < 6; ++i) V[i] += u0[i];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) bs[i] += u0[6 + i];
+                if (two) {
+#pragma unroll
+                    for (int i = 0; i < 6; ++i) V[i] += u1[i];
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) bs[i] += u1[6 + i];
+                }
             }
         }
         double Li[6] = {0, 0, 0, 0, 0, 0};
@@ -796,6 +854,29 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             }
         } else {
             __syncthreads();   // Z staged
+            if (kPre) {   // the next chunk's observations and positions
+                pre = nxt;
+                if (nxt) {
+                    const int o = (int)hdr.w + tid;
+                    if (o < a.sobs.n_obs) {
+                        pf_kf = a.sobs.kf[o];
+                        pf_flag = (a.smask ? a.smask : a.sobs.type)[o];
+                        pf_type = a.sobs.type[o];
+                        pf_oct = a.sobs.oct[o];
+                        const ZT *z = static_cast<const ZT *>(a.sobs.z);
+                        pf_z0 = z[o];
+                        pf_z1 = z[(int64_t)a.sobs.n_obs + o];
+                        pf_z2 = z[2 * (int64_t)a.sobs.n_obs + o];
+                    }
+                    if (q + tid < tile.p1) {
+                        const int64_t P = pin.x;
+                        pf_X0 = Xs[3 * P];
+                        pf_X1 = Xs[3 * P + 1];
+                        pf_X2 = Xs[3 * P + 2];
+                    }
+                    load_words(tid);   // (this chunk's words are in LDS since phase 1)
+                }
+            }
         }
 
         // ---- 4. piece products, PB at a time, then each owner sums its rows --------------
