@@ -58,9 +58,10 @@ struct LinCfg {
     static constexpr int PCAP = sizeof(Real) == 4 ? 3072 : 2080;   // pairs per chunk (>= 64*65/2)
     static constexpr int PB = 256;                             // pieces per batch
     static constexpr int kPiece = sizeof(Real) == 4 ? 8 : 4;   // pairs per piece (measured best)
-    // FP32 chunks whose pieces of kPieceSmall pairs fit one batch use those instead: the
-    // batch then costs each lane kPieceSmall pair products rather than kPiece
-    static constexpr int kPieceSmall = sizeof(Real) == 4 ? 6 : 4;
+    // An FP32 chunk takes the smallest piece of 4, 5 or 6 pairs whose pieces fit one batch
+    // (else pieces of kPiece): a batch costs each lane kp pair products, and every thread
+    // pair of the block then holds a piece
+    static constexpr bool kAdaptive = sizeof(Real) == 4;
     static constexpr int PS = 37;                              // product row stride (odd)
     // Z row stride in values: 19 (odd) rather than 18, so that the rows the lanes of a
     // wavefront gather by pair start in twice as many distinct LDS banks
@@ -75,7 +76,7 @@ struct LinSmem {
     double *T;       // K x 12 poses, then 34 weights: 1 / sigma2 per octave (32), Huber
                      // thresholds mono, stereo
     int *opt;        // K
-    Real *Z;         // CO x ZS (18 values per observation)
+    Real *Z;         // (CO + 1) x ZS (18 values per observation; row CO stays zero)
     double *hs;      // CO x 9    FP64 Hll_a (6) and bl_a (3) for the point sums
     int *ints;       // the chunk's observation ranges and points (phases 1-2)
     double *dacc;    // copies x Kopt x 27: per copy (wavefront, or one for the block) and
@@ -121,18 +122,22 @@ __device__ __forceinline__ void piece_product(const LinSmem<Real> &sm, int r0, i
         Real own[9], oth[9];   // [i][jj]: row R0 + i of the sum, column R0 + jj / R1 + jj
 #pragma unroll
         for (int c = 0; c < 9; ++c) own[c] = oth[c] = (Real)0;
+        // a piece of fewer than NP pairs is filled up with the zero row (row CO of Z)
+        constexpr unsigned kZeroPair = (unsigned)LinCfg<Real>::CO | ((unsigned)LinCfg<Real>::CO << 10);
         unsigned e[NP];
 #pragma unroll
-        for (int u = 0; u < NP; ++u) e[u] = sm.pairs[min(r0 + u, r1 - 1)];
+        for (int u = 0; u < NP; ++u) {
+            const unsigned ev = sm.pairs[min(r0 + u, r1 - 1)];
+            e[u] = r0 + u < r1 ? ev : kZeroPair;
+        }
 #pragma unroll
         for (int u = 0; u < NP; ++u) {
-            const Real wgt = r0 + u < r1 ? (Real)1 : (Real)0;
             constexpr int ZS = LinCfg<Real>::ZS;
             const Real *za = sm.Z + (e[u] & 1023) * ZS + R0 * 3, *zb = sm.Z + ((e[u] >> 10) & 1023) * ZS + R0 * 3;
             Real ai[9], bh[9], bo[9];
 #pragma unroll
             for (int c = 0; c < 9; ++c) {
-                ai[c] = za[c] * wgt;
+                ai[c] = za[c];
                 bh[c] = zb[c];
             }
 #pragma unroll
@@ -202,7 +207,7 @@ __host__ __device__ inline size_t lin_carve(unsigned char *base, int K, int Kopt
     auto take = [&](size_t bytes) { void *p = base ? (void *)(base + o) : nullptr; o = align_up(o + bytes, 16); return p; };
     void *T = take(sizeof(double) * (12 * K + kMaxLevels + 2));
     void *opt = take(sizeof(int) * K);
-    void *Z = take(sizeof(Real) * C::CO * C::ZS);
+    void *Z = take(sizeof(Real) * (C::CO + 1) * C::ZS);   // row CO: zeros
     // the staging of phases 1-2 (point-sum terms, then the chunk's observation ranges
     // (513), first observations and indices of its points (512 each) and the point of
     // each observation slot (CO), see the kernel) and the piece products of phase 4 share
@@ -272,6 +277,41 @@ __device__ __forceinline__ long long block_inclusive_scan64(long long v, int *sc
         add += w < wave ? u : 0;
     }
     return x + add;
+}
+
+// inclusive scan of one 64-bit value per thread over the block (512 threads), and the
+// block's total.  The caller places a barrier between this and the next writer of scan[].
+__device__ __forceinline__ unsigned long long block_inclusive_scan64_total(unsigned long long v, int *scan, int tid,
+                                                                           unsigned long long &total) {
+    const int lane = tid & 63, wave = tid >> 6;
+    unsigned long long x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned long long y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    unsigned long long *sc = reinterpret_cast<unsigned long long *>(scan);
+    if (lane == 63) sc[wave] = x;
+    __syncthreads();
+    unsigned long long add = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kNT / 64; ++w) {
+        const unsigned long long u = sc[w];
+        add += w < wave ? u : 0ull;
+        tot += u;
+    }
+    total = tot;
+    return x + add;
+}
+
+// piece of the pair of rank rk in its block (constant divisors)
+__device__ __forceinline__ int piece_of(int rk, int kp) {
+    switch (kp) {
+        case 4: return rk / 4;
+        case 5: return rk / 5;
+        case 6: return rk / 6;
+        default: return rk / 8;
+    }
 }
 
 // inclusive scan of one int per thread over the block (512 threads).  The caller places a
@@ -356,7 +396,8 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
     // The first launch of a round forms them (phases 1-3 below) and stores one record per
     // chunk in the pool while it has room; later launches of the round load the records
     // instead of forming them.  A record: next record (word offset, ~0 for none), end
-    // point of the chunk, pairs | pieces << 12 | (pieces of kPieceSmall) << 22, place of
+    // point of the chunk, pairs | pieces << 12 | code << 22 (pieces of 3 + code pairs, or
+    // of kPiece for code 0), place of
     // the chunk's first observation; then the pairs, the piece starts (16-bit) and the
     // blocks' piece offsets (16-bit).
     const int slot = t * (int)gridDim.y + (int)blockIdx.y;
@@ -399,6 +440,7 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
     const int ncopy = a.self_copies;
     Acc *const dacc = reinterpret_cast<Acc *>(sm.dacc);
     for (int i = tid; i < ncopy * Kopt * 27; i += kNT) dacc[i] = (Acc)0;
+    if (tid < C::ZS) sm.Z[C::CO * C::ZS + tid] = (Real)0;   // the zero row that fills pieces
     __syncthreads();
 
     const CamParams cam = a.c.cam;
@@ -448,7 +490,7 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
             q = (int)hdr.y;
             npr = (int)(hdr.z & 4095u);
             nwc = (int)((((hdr.z >> 12) & 1023u) + 2u) >> 1);
-            if (C::kPieceSmall != C::kPiece && ((hdr.z >> 22) & 1u)) kp = C::kPieceSmall;
+            if (C::kAdaptive && ((hdr.z >> 22) & 3u)) kp = 3 + (int)((hdr.z >> 22) & 3u);
             ntot = npr + nwc + ((nblk + 2) >> 1);
             if ((int64_t)recw + 4 + ntot > a.plan_cap) ntot = 0;   // (the pool's bound; fails below)
             if (!(kPre && pre)) load_words(tid);
@@ -732,28 +774,33 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
                 }
             }
             __syncthreads();
-            if constexpr (C::kPieceSmall != C::kPiece) {
-                // pair offsets (bits 0-11, at most PCAP = 3072), piece offsets for kPieceSmall
-                // (bits 12-21) and for kPiece (bits 22-31) in one scan: a block of c pairs has
-                // at most c / kPiece + 1 pieces, so each piece field stays below
-                // PCAP / kPieceSmall + kPassBlocks = 988 < 1024
-                static_assert(C::PCAP < 4096 && C::PCAP / C::kPieceSmall + kPassBlocks < 1024, "scan fields");
-                const unsigned c = tid < nblk ? (unsigned)sm.cnt[tid] : 0u;
-                const unsigned v = c | (((c + C::kPieceSmall - 1) / C::kPieceSmall) << 12) |
-                                   (((c + C::kPiece - 1) / C::kPiece) << 22);
-                unsigned tot;
-                const unsigned incl = block_inclusive_scan_total(v, sm.scan, tid, tot);
-                const bool small = ((tot >> 12) & 1023u) <= (unsigned)C::PB;
-                kp = small ? C::kPieceSmall : C::kPiece;
-                const int sh = small ? 12 : 22;
+            if constexpr (C::kAdaptive) {
+                // pair offsets (bits 0-11, at most PCAP = 3072) and the piece offsets for
+                // pieces of 4 (bits 12-22), 5 (23-33), 6 (34-43) and 8 pairs (44-53) in one
+                // scan: a block of c pairs has at most c / kp + 1 pieces, so the fields stay
+                // below PCAP / kp + kPassBlocks (1,244, 1,090, 988, 860)
+                static_assert(C::PCAP < 4096 && C::PCAP / 4 + kPassBlocks < 2048 && C::PCAP / 6 + kPassBlocks < 1024,
+                              "scan fields");
+                const unsigned long long c = tid < nblk ? (unsigned long long)sm.cnt[tid] : 0ull;
+                const unsigned long long v = c | (((c + 3) / 4) << 12) | (((c + 4) / 5) << 23) | (((c + 5) / 6) << 34) |
+                                             (((c + 7) / 8) << 44);
+                unsigned long long tot;
+                const unsigned long long incl = block_inclusive_scan64_total(v, sm.scan, tid, tot);
+                const unsigned long long ex = incl - v;
+                int sh = 44, mask = 1023;
+                kp = 8;
+                if (((tot >> 34) & 1023ull) <= (unsigned long long)C::PB) { kp = 6; sh = 34; }
+                if (((tot >> 23) & 2047ull) <= (unsigned long long)C::PB) { kp = 5; sh = 23; mask = 2047; }
+                if (((tot >> 12) & 2047ull) <= (unsigned long long)C::PB) { kp = 4; sh = 12; mask = 2047; }
                 if (tid < nblk) {
-                    sm.cnt[tid] = (int)((incl - v) & 4095u);
-                    pco[tid] = (int)(((incl - v) >> sh) & 1023u);
+                    sm.cnt[tid] = (int)(ex & 4095ull);
+                    pco[tid] = (int)((ex >> sh) & (unsigned long long)mask);
                 }
                 if (tid == nblk - 1) {
-                    sm.cnt[nblk] = (int)(incl & 4095u);
-                    pco[nblk] = (int)((incl >> sh) & 1023u);
-                    pcs[(incl >> sh) & 1023u] = (unsigned short)(incl & 4095u);
+                    const int np_ = (int)((incl >> sh) & (unsigned long long)mask);
+                    sm.cnt[nblk] = (int)(incl & 4095ull);
+                    pco[nblk] = np_;
+                    pcs[np_] = (unsigned short)(incl & 4095ull);
                 }
             } else {   // pair offsets (low half) and piece offsets (high half) in one scan
                 const int c = tid < nblk ? sm.cnt[tid] : 0;
@@ -789,7 +836,7 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
                 const int pos = sm.cnt[B] + rk;
                 sm.pairs[pos] = (unsigned)first | ((unsigned)second << 10) | (fl << 20);
                 if (C::kPiece > 1) {
-                    const int pq = kp == C::kPiece ? rk / C::kPiece : rk / C::kPieceSmall;
+                    const int pq = piece_of(rk, kp);
                     if (rk == pq * kp) pcs[pco[B] + pq] = (unsigned short)pos;
                 }
             };
@@ -842,7 +889,7 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
                         dst[4 + npr_c + nwc_c + i] =
                             (uint32_t)pco[2 * i] | ((2 * i + 1 <= nblk ? (uint32_t)pco[2 * i + 1] : 0u) << 16);
                     if (tid == 0) {
-                        const uint32_t sm_flag = (C::kPieceSmall != C::kPiece && kp == C::kPieceSmall) ? 1u : 0u;
+                        const uint32_t sm_flag = (C::kAdaptive && kp < C::kPiece) ? (uint32_t)(kp - 3) : 0u;
                         *reinterpret_cast<uint4 *>(dst) =
                             make_uint4(0xffffffffu, (uint32_t)q, (uint32_t)npr_c | ((uint32_t)npc_c << 12) | (sm_flag << 22),
                                        (uint32_t)gst[0]);
@@ -898,10 +945,14 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
                             __hip_atomic_fetch_or(&touch[B % kGroups], 1ull << (B / kGroups), __ATOMIC_RELAXED,
                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
                     }
-                    if (C::kPieceSmall == C::kPiece || kp == C::kPiece)
+                    if constexpr (C::kAdaptive) {
+                        if (kp == 4) piece_product<Real, 4>(sm, r0, r1, fl, h, out);
+                        else if (kp == 5) piece_product<Real, 5>(sm, r0, r1, fl, h, out);
+                        else if (kp == 6) piece_product<Real, 6>(sm, r0, r1, fl, h, out);
+                        else piece_product<Real, C::kPiece>(sm, r0, r1, fl, h, out);
+                    } else {
                         piece_product<Real, C::kPiece>(sm, r0, r1, fl, h, out);
-                    else
-                        piece_product<Real, C::kPieceSmall>(sm, r0, r1, fl, h, out);
+                    }
                 }
             }
             __syncthreads();
