@@ -83,10 +83,10 @@ constexpr int kCholThreads = 512;
 
 size_t chol_lds_bytes(int n) {
     const size_t E = (size_t)n * (n + 1) / 2;
-    return sizeof(double) * (E + 3 * (size_t)n + (size_t)kNB * n) + 64;
+    return sizeof(double) * (E + 4 * (size_t)n + (size_t)kNB * n) + 64;
 }
 
-size_t chol_lds_bytes_hbm(int n) { return sizeof(double) * (3 * (size_t)n + (size_t)kNB * n) + 64; }
+size_t chol_lds_bytes_hbm(int n) { return sizeof(double) * (4 * (size_t)n + (size_t)kNB * n) + 64; }
 
 __device__ __forceinline__ void tri_decode(int e, int &ii, int &jj) {
     int r = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
@@ -147,11 +147,27 @@ __global__ __launch_bounds__(kCholThreads) void k_cholesky(CholArgs a) {
     double *rr = y + n;      // n: copy of the right side (gain-ratio denominator)
     double *rdiag = rr + n;  // n reciprocal pivots
     double *Ld = rdiag + n;  // n x kNB: factored diagonal blocks (row r holds L[r][c0 .. r])
+    double *xs = Ld + (size_t)n * kNB;   // n: the solution of L^T x = y
     const double *red = a.red + W.red_off;
-    for (int i = tid; i < E; i += nth) A[i] = red[i];
-    for (int i = tid; i < n; i += nth) {
-        y[i] = red[E + i];
-        rr[i] = red[E + i];
+    // eight loads in flight per thread (one at a time, each waited on before its store,
+    // took a memory round trip per 512 entries)
+    for (int i0 = tid; i0 < E + n; i0 += 8 * nth) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u * nth;
+            v[u] = i < E + n ? red[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u * nth;
+            if (i < E) {
+                A[i] = v[u];
+            } else if (i < E + n) {
+                y[i - E] = v[u];
+                rr[i - E] = v[u];
+            }
+        }
     }
     if (tid == 0) s_fail = a.redflag[w] != 0.0;
     __syncthreads();
@@ -263,6 +279,9 @@ __global__ __launch_bounds__(kCholThreads) void k_cholesky(CholArgs a) {
     const int ok = !s_fail;
 
     // ---- L^T x = y (y was solved with the factorisation; one barrier per panel) ------
+    // Each panel's entries of x go to their own array, so the threads still reading the
+    // panel's y are not overtaken by its solution; the rows above are updated in the same
+    // step.
     if (ok) {
         const int last = n > 0 ? ((n - 1) / kNB) * kNB : 0;
         for (int c0 = last; c0 >= 0 && n > 0; c0 -= kNB) {
@@ -283,13 +302,12 @@ __global__ __launch_bounds__(kCholThreads) void k_cholesky(CholArgs a) {
                 for (int k = j + 1; k < kNB; ++k) v -= Lb[k][j] * xp[k];
                 xp[j] = v * rb[j];
             }
-            __syncthreads();
             if (tid < nbk) {
                 double v = 0.0;
 #pragma unroll
                 for (int j = 0; j < kNB; ++j)
                     if (j == tid) v = xp[j];
-                y[c0 + tid] = v;
+                xs[c0 + tid] = v;
             }
             for (int j = tid; j < c0; j += nth) {
                 double acc = 0.0;
@@ -305,7 +323,7 @@ __global__ __launch_bounds__(kCholThreads) void k_cholesky(CholArgs a) {
     if (tid < 64) {
         double den = 0.0;
         for (int i = lane; i < n; i += 64) {
-            const double x = ok ? y[i] : 0.0;
+            const double x = ok ? xs[i] : 0.0;
             dp[i] = x;
             den += x * (lambda * x + rr[i]);   // + point part in the update kernel
         }
