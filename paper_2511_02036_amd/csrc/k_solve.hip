@@ -61,30 +61,25 @@ hipError_t launch_reduce(const ReduceArgs &a, int n_windows, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------------------------
-// Dense FP64 Cholesky of S + lambda I and the two triangular solves, one block of 512
-// threads per window, S held as a packed lower triangle in LDS.  Right-looking with
-// 8-column panels.  Per panel every thread reads the 8x8 diagonal block (broadcast LDS
-// reads) and factors it redundantly in registers, so no lane-to-lane traffic sits on the
+// Dense FP64 Cholesky of S + lambda I and the two triangular solves for systems too large
+// for the register-tile variant below (more than 216 unknowns): one block of 512 threads
+// per window, S held as a packed lower triangle in a per-window copy in HBM, which one
+// block keeps hot in its XCD's L2 (kHbm; the template also keeps the LDS-resident form).
+// Right-looking with 8-column panels.  Per panel every thread reads the 8x8 diagonal
+// block and factors it redundantly in registers, so no lane-to-lane traffic sits on the
 // serial path; each thread then solves one row of the panel below the block, and after
 // one barrier all threads apply the rank-8 update to the trailing triangle in 4x4
 // register tiles.  The forward solve L y = r rides along: every thread also solves the
 // panel's 8 entries of y redundantly, and the thread of each row below subtracts its
 // share.  The backward solve walks the panels from the last, every thread solving the
 // panel's 8 entries from prefetched registers, then all threads updating the rows above.
-// A system too large for LDS (n above about 180) is factored the same way in a per-window
-// copy in HBM (kHbm), which one block keeps hot in its XCD's L2; the right side, the
-// pivots and the factored diagonal blocks stay in LDS.
+// The right side, the pivots and the factored diagonal blocks stay in LDS.
 // ------------------------------------------------------------------------------------
 #ifndef LBA_CHOL_NB
 #define LBA_CHOL_NB 8
 #endif
 constexpr int kNB = LBA_CHOL_NB;
 constexpr int kCholThreads = 512;
-
-size_t chol_lds_bytes(int n) {
-    const size_t E = (size_t)n * (n + 1) / 2;
-    return sizeof(double) * (E + 4 * (size_t)n + (size_t)kNB * n) + 64;
-}
 
 size_t chol_lds_bytes_hbm(int n) { return sizeof(double) * (4 * (size_t)n + (size_t)kNB * n) + 64; }
 
@@ -335,14 +330,231 @@ __global__ __launch_bounds__(kCholThreads) void k_cholesky(CholArgs a) {
     }
 }
 
-size_t chol_static_lds() {
-    return std::max(kernel_static_lds((const void *)k_cholesky<false>), kernel_static_lds((const void *)k_cholesky<true>));
+
+// ------------------------------------------------------------------------------------
+// The same factorisation and solves for systems of up to 216 unknowns with the matrix in
+// registers: S + lambda I is cut into 4 x 4 tiles of its lower triangle, and thread t
+// owns tiles t, t + 512 and t + 1024 (packed row-major tile order) for the whole solve,
+// so the trailing updates read only the panel from LDS and write nothing there.  Per
+// panel of four columns:
+//   1. the owner of the diagonal tile factors it (and solves the panel's entries of y),
+//      and publishes the factor;
+//   2. the owners of the tiles below it solve them against the factor (their rows of the
+//      panel, published to LDS) and subtract their share of y;
+//   3. every owner of a trailing tile subtracts the product of its two panel rows.
+// The panel and the factor are double-buffered, so two barriers per panel suffice.  The
+// back solve L^T x = y walks the panels from the last: the diagonal owner solves the
+// panel's x, then the owners of the tiles left of the diagonal subtract their share from
+// y.  Every sum is taken in a fixed order, so solves repeat bit for bit.  Rows past n are
+// an identity block with a zero right side.
+// ------------------------------------------------------------------------------------
+constexpr int kRegMaxN = 216;                  // 54 tile rows, 1,485 tiles <= 3 x 512
+constexpr int kRegThreads = 512;
+constexpr int kRegSlots = 3;
+
+int chol_reg_max_n() { return kRegMaxN; }
+
+__global__ __launch_bounds__(kRegThreads) void k_chol_reg(CholArgs a) {
+    __shared__ double P[2][kRegMaxN][4];   // panel rows: L[r][4k .. 4k + 3]
+    __shared__ double Lk[2][16];           // factored diagonal tile (row-major 4 x 4)
+    __shared__ double Rk[2][4];            // its reciprocal pivots
+    __shared__ double y[kRegMaxN], xs[kRegMaxN], rr[kRegMaxN], rdg[kRegMaxN];
+    __shared__ int s_fail;
+    const int w = blockIdx.x;
+    const WinInfo W = a.win[w];
+    Ctl *ctl = a.ctl + w;
+    if (!ctl->running) return;
+    const int n = W.n, E = W.E;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const double lambda = ctl->lambda;
+    const double *red = a.red + W.red_off;
+    const int NT = (n + 3) / 4, N4 = 4 * NT;
+    const int ntiles = NT * (NT + 1) / 2;
+    if (tid == 0) s_fail = (a.redflag[w] != 0.0) || n > kRegMaxN;
+    // right side (padded with zeros)
+    for (int i = tid; i < N4; i += kRegThreads) {
+        const double v = i < n ? red[E + i] : 0.0;
+        y[i] = v;
+        rr[i] = v;
+    }
+    // own tiles: loads issued for all three before any is used
+    int tI[kRegSlots], tJ[kRegSlots];
+    double T[kRegSlots][4][4];
+#pragma unroll
+    for (int u = 0; u < kRegSlots; ++u) {
+        const int t = tid + kRegThreads * u;
+        int I = -1, J = -1;
+        if (t < ntiles) tri_decode(t, I, J);
+        tI[u] = I;
+        tJ[u] = J;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int i = 4 * I + r, j = 4 * J + c;
+                double v = 0.0;
+                if (I >= 0 && i < n && j <= i) v = red[packed_lower(i, j)] + (i == j ? lambda : 0.0);
+                else if (I >= 0 && i == j) v = 1.0;   // padding rows: identity
+                T[u][r][c] = v;
+            }
+    }
+    __syncthreads();
+    // (s_fail is read only right after a barrier that follows its last write: a thread
+    // that read it while another sets it would leave the panel loop alone)
+    const bool failed_before = s_fail != 0;
+
+    // ---- factorisation and forward solve ----------------------------------------------
+    for (int k = 0; k < NT && !failed_before; ++k) {
+        const int b = k & 1;
+        // 1. the diagonal tile
+#pragma unroll
+        for (int u = 0; u < kRegSlots; ++u) {
+            if (tI[u] != k || tJ[u] != k) continue;
+            double rd[4];
+            bool ok = true;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                double d = T[u][c][c];
+#pragma unroll
+                for (int m = 0; m < c; ++m) d -= T[u][c][m] * T[u][c][m];
+                if (!(d > 0.0) || !isfinite(d)) ok = false;
+                const double r = rsqrt(d);
+                T[u][c][c] = d * r;
+                rd[c] = r;
+#pragma unroll
+                for (int q = c + 1; q < 4; ++q) {
+                    double v = T[u][q][c];
+#pragma unroll
+                    for (int m = 0; m < c; ++m) v -= T[u][q][m] * T[u][c][m];
+                    T[u][q][c] = v * r;
+                }
+            }
+            double yk[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                double v = y[4 * k + c];
+#pragma unroll
+                for (int m = 0; m < c; ++m) v -= T[u][c][m] * yk[m];
+                yk[c] = v * rd[c];
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) Lk[b][4 * r + c] = c <= r ? T[u][r][c] : 0.0;
+                Rk[b][r] = rd[r];
+                rdg[4 * k + r] = rd[r];
+                y[4 * k + r] = yk[r];
+            }
+            if (!ok) s_fail = 1;
+        }
+        __syncthreads();
+        if (s_fail) break;
+        // 2. the tiles below the diagonal tile: L_Ik = A_Ik L_kk^-T
+        double lk[16], rk[4], yk[4];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) lk[q] = Lk[b][q];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            rk[c] = Rk[b][c];
+            yk[c] = y[4 * k + c];
+        }
+#pragma unroll
+        for (int u = 0; u < kRegSlots; ++u) {
+            if (tJ[u] != k || tI[u] <= k) continue;
+            const int I = tI[u];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                double dy = 0.0;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    double v = T[u][r][c];
+#pragma unroll
+                    for (int m = 0; m < c; ++m) v -= T[u][r][m] * lk[4 * c + m];
+                    T[u][r][c] = v * rk[c];
+                    P[b][4 * I + r][c] = T[u][r][c];
+                    dy += T[u][r][c] * yk[c];
+                }
+                y[4 * I + r] -= dy;   // the only writer of these rows in this panel
+            }
+        }
+        __syncthreads();
+        // 3. trailing tiles (J > k): A_IJ -= L_Ik L_Jk^T
+#pragma unroll
+        for (int u = 0; u < kRegSlots; ++u) {
+            if (tJ[u] <= k) continue;
+            const int I = tI[u], J = tJ[u];
+            double pi[4][4], pj[4][4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    pi[r][c] = P[b][4 * I + r][c];
+                    pj[r][c] = P[b][4 * J + r][c];
+                }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    T[u][r][c] -= pi[r][0] * pj[c][0] + pi[r][1] * pj[c][1] + pi[r][2] * pj[c][2] + pi[r][3] * pj[c][3];
+        }
+    }
+    __syncthreads();
+    const int ok = !s_fail;
+
+    // ---- back solve L^T x = y, two barriers per panel -----------------------------------
+    if (ok) {
+        for (int k = NT - 1; k >= 0; --k) {
+#pragma unroll
+            for (int u = 0; u < kRegSlots; ++u) {
+                if (tI[u] != k || tJ[u] != k) continue;
+                double xk[4];
+#pragma unroll
+                for (int c = 3; c >= 0; --c) {
+                    double v = y[4 * k + c];
+#pragma unroll
+                    for (int m = c + 1; m < 4; ++m) v -= T[u][m][c] * xk[m];
+                    xk[c] = v * rdg[4 * k + c];
+                }
+#pragma unroll
+                for (int c = 0; c < 4; ++c) xs[4 * k + c] = xk[c];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < kRegSlots; ++u) {
+                if (tI[u] != k || tJ[u] >= k) continue;
+                const int J = tJ[u];
+                double xk[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) xk[r] = xs[4 * k + r];
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    y[4 * J + c] -= T[u][0][c] * xk[0] + T[u][1][c] * xk[1] + T[u][2][c] * xk[2] + T[u][3][c] * xk[3];
+            }
+            __syncthreads();
+        }
+    }
+    double *dp = a.dp + W.dp_off;
+    if (tid < 64) {
+        double den = 0.0;
+        for (int i = lane; i < n; i += 64) {
+            const double x = ok ? xs[i] : 0.0;
+            dp[i] = x;
+            den += x * (lambda * x + rr[i]);   // + point part in the update kernel
+        }
+        den = wave_sum(den);
+        if (lane == 0) {
+            ctl->solve_ok = ok;
+            ctl->denom_p = den;
+        }
+    }
 }
+
+size_t chol_static_lds() { return kernel_static_lds((const void *)k_cholesky<true>); }
 
 hipError_t launch_cholesky(const CholArgs &a, int n_windows, size_t lds, hipStream_t s) {
     if (n_windows <= 0) return hipSuccess;
     if (a.fact) hipLaunchKernelGGL(k_cholesky<true>, dim3(n_windows), dim3(kCholThreads), lds, s, a);
-    else hipLaunchKernelGGL(k_cholesky<false>, dim3(n_windows), dim3(kCholThreads), lds, s, a);
+    else hipLaunchKernelGGL(k_chol_reg, dim3(n_windows), dim3(kRegThreads), 0, s, a);
     return hipGetLastError();
 }
 

@@ -344,9 +344,10 @@ lba_status build_plan(lba_ctx *ctx, const lba_problem *P, const lba_batch *B, Pl
         if (vred > INT32_MAX) return set_error(ctx, LBA_ERR_UNSUPPORTED, "batch too large");
     }
     // the reduced system is factored in LDS when it fits, else in a per-window copy in HBM
-    pl.chol_lds = chol_lds_bytes(maxn);
-    pl.chol_hbm = pl.chol_lds + chol_static_lds() > (size_t)ctx->max_lds;
-    if (pl.chol_hbm) pl.chol_lds = chol_lds_bytes_hbm(maxn);
+    // (systems of up to chol_reg_max_n() unknowns are factored with the matrix in registers
+    // and static LDS only; larger ones in a per-window copy in HBM)
+    pl.chol_hbm = maxn > chol_reg_max_n();
+    pl.chol_lds = pl.chol_hbm ? chol_lds_bytes_hbm(maxn) : 0;
     if (pl.chol_lds + chol_static_lds() > (size_t)ctx->max_lds || (pl.chol_hbm && pl.vi))
         return set_error(ctx, LBA_ERR_UNSUPPORTED, "reduced system of %d unknowns does not fit in LDS", maxn);
     pl.lin_passes = lin_passes(pl.max_kopt);

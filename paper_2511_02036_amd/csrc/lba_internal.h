@@ -322,6 +322,7 @@ hipError_t launch_init(const LinArgs &a, int ntiles, size_t lds, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs &a, int n_windows, hipStream_t s);
 hipError_t launch_cholesky(const CholArgs &a, int n_windows, size_t lds, hipStream_t s);
 size_t chol_lds_bytes_hbm(int n);   // LDS of the variant whose matrix is in HBM
+int chol_reg_max_n();               // largest system the register-tile variant factors
 hipError_t launch_decide(const DecideArgs &a, int n_windows, hipStream_t s);
 hipError_t launch_init_reduce(const InitReduceArgs &a, int n_windows, hipStream_t s);
 hipError_t launch_setup(const MiscArgs &a, int n_windows, hipStream_t s);
@@ -347,7 +348,6 @@ size_t cost_static_lds();
 size_t lin_lds_bytes(int K, int kopt, int copies, bool mixed);
 int lin_self_copies(bool mixed);   // copies of the camera sums for bitwise-repeatable solves
 size_t upd_lds_bytes(int K, int n, int waves, bool mixed);
-size_t chol_lds_bytes(int n);
 size_t cost_lds_bytes(int K, bool backward);
 size_t init_lds_bytes(int K, int n);
 
