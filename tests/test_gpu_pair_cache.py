@@ -70,3 +70,23 @@ def test_records_with_several_passes_match_the_oracle(kopt):
     for cache in (1, 0):
         g = lba.solve(w, device="cuda:0", pair_cache=cache)
         assert_fp64_parity(w, g["T"], g["X"], g["outlier"], g["stats"][0], r)
+
+
+def test_records_that_overflow_the_pool_fall_back_to_forming_them():
+    """Points seen by about 24 of 25 optimisable keyframes (an arc facing inward) have about 11
+    pairs per observation, more than the pool holds (8 words per observation and 256 per 256
+    observations and per tile): the tiles whose records do not fit form them at every step,
+    and the solve is the same as without records (25 optimisable keyframes: the camera sums
+    keep one copy per wavefront, so both are bitwise-repeatable)."""
+    w = synth.make_window(np.random.default_rng(91), trajectory="arc", K=26, n_fixed=1, M=500, nobs=(24, 26),
+                          stereo_p=0.6)
+    on = np.asarray(w["fixed"])[w["obs_kf"]] == 0
+    m = np.bincount(w["obs_pt"][on], minlength=len(w["X"]))
+    pairs, n = int((m * (m - 1) // 2).sum()), len(w["obs_kf"])
+    print(f"case pair_cache overflow N={n} pairs={pairs}", flush=True)
+    assert pairs > 8 * n + 256 * (n // 256 + 8)   # more pair words than the whole pool
+    a = lba.solve(w, device="cuda:0", pair_cache=1)
+    b = lba.solve(w, device="cuda:0", pair_cache=0)
+    _same(a, b)
+    r = lbaref.solve(w)
+    assert_fp64_parity(w, a["T"], a["X"], a["outlier"], a["stats"][0], r)
