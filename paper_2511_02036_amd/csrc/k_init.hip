@@ -20,7 +20,7 @@ constexpr int kInitWaves = kInitThreads / kWave;
 static __host__ __device__ inline size_t init_align(size_t x) { return (x + 15) / 16 * 16; }
 
 size_t init_lds_bytes(int K, int n) {
-    size_t o = init_align(sizeof(double) * 12 * K);          // poses
+    size_t o = init_align(sizeof(double) * (12 * K + kMaxLevels + 2));   // poses, weights
     o += init_align(sizeof(int) * K);                          // optimisable index
     o += init_align(sizeof(double) * kInitWaves * (n > 0 ? n : 1));   // per-wave camera rows
     o += init_align(sizeof(double) * kInitWaves * 64 * 3);     // point-block diagonals
@@ -39,7 +39,8 @@ __global__ __launch_bounds__(kInitThreads) void k_init(LinArgs a) {
     const int K = W.K, n = W.n;
     unsigned char *cur = smem;
     double *T = reinterpret_cast<double *>(cur);
-    cur += init_align(sizeof(double) * 12 * K);
+    double *wt = T + 12 * K;   // 1 / sigma2 per octave (32), Huber thresholds mono, stereo
+    cur += init_align(sizeof(double) * (12 * K + kMaxLevels + 2));
     int *opt = reinterpret_cast<int *>(cur);
     cur += init_align(sizeof(int) * K);
     double *hdw = reinterpret_cast<double *>(cur);
@@ -55,6 +56,9 @@ __global__ __launch_bounds__(kInitThreads) void k_init(LinArgs a) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int i = tid; i < 12 * K; i += kInitThreads) T[i] = a.T[(int64_t)W.kf0 * 12 + i];
     for (int i = tid; i < K; i += kInitThreads) opt[i] = a.opt_map[W.kf0 + i];
+    // the weights by octave and type, read per observation: from LDS rather than from the
+    // kernel arguments (one dependent memory round trip less per chunk)
+    if (tid < kMaxLevels + 2) wt[tid] = tid < kMaxLevels ? a.c.inv_sigma2[tid] : a.c.huber2[tid - kMaxLevels];
     for (int i = tid; i < kInitWaves * n; i += kInitThreads) hdw[i] = 0.0;
     __syncthreads();
 
@@ -96,7 +100,10 @@ __global__ __launch_bounds__(kInitThreads) void k_init(LinArgs a) {
         if (o < a.obs.n_obs) {
             jl = a.obs.pt[o];
             kl = a.obs.kf[o];
-            act = !a.mask || !a.mask[o];
+            // the flag is loaded without a branch (from a readable byte array when there
+            // is none), so that it issues with the other loads
+            const uint8_t flag = (a.mask ? a.mask : a.obs.type)[o];
+            act = (a.mask == nullptr) | (flag == 0);
             stereo = a.obs.type[o];
             oct = a.obs.oct[o];
             if (a.obs.z_f32) load_z<float>(a.obs, o, zu, zv, zr);
@@ -116,9 +123,9 @@ __global__ __launch_bounds__(kInitThreads) void k_init(LinArgs a) {
                 double xc, yc, zc, eu, ev, er;
                 const double e2 = residual(cam, Tk, xs[3 * pl], xs[3 * pl + 1], xs[3 * pl + 2], zu, zv, zr, stereo,
                                            xc, yc, zc, eu, ev, er);
-                const double isg = a.c.inv_sigma2[oct];
+                const double isg = wt[oct];
                 double rho, w;
-                huber(e2 * isg, a.c.huber2[stereo], a.robust, rho, w);
+                huber(e2 * isg, wt[kMaxLevels + stereo], a.robust, rho, w);
                 F += rho;
                 const double om = w * isg;
                 const double iz = 1.0 / zc, sf = stereo ? 1.0 : 0.0;

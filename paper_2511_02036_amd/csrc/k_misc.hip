@@ -133,6 +133,12 @@ hipError_t launch_validate(const MiscArgs &a, int n_windows, int64_t max_obs, hi
 // With a.count set, each wavefront also adds its number of flagged observations to the
 // window's control block (integer atomics: the total does not depend on their order).
 __global__ void k_flags(MiscArgs a) {
+    // the weights by octave and the thresholds by type, read per observation: from LDS
+    // rather than from the kernel arguments (one dependent memory round trip less)
+    __shared__ double wt[kMaxLevels + 2];
+    if (threadIdx.x < kMaxLevels + 2)
+        wt[threadIdx.x] = threadIdx.x < kMaxLevels ? a.c.inv_sigma2[threadIdx.x] : a.c.chi2[threadIdx.x - kMaxLevels];
+    __syncthreads();
     const int w = blockIdx.y;
     const int64_t o0 = a.obs_off_dev[w], o1 = a.obs_off_dev[w + 1];
     Ctl &c = a.ctl[w];
@@ -151,8 +157,8 @@ __global__ void k_flags(MiscArgs a) {
         double xc, yc, zc, eu, ev, er;
         const double e2 = residual(a.c.cam, a.T + 12 * (int64_t)kf, X[3 * pt], X[3 * pt + 1], X[3 * pt + 2],
                                    u, v, ur, stereo, xc, yc, zc, eu, ev, er);
-        const double s = e2 * a.c.inv_sigma2[a.obs.oct[o]];
-        const int f = (s > a.c.chi2[stereo] || zc <= 0.0) ? 1 : 0;
+        const double s = e2 * wt[a.obs.oct[o]];
+        const int f = (s > wt[kMaxLevels + stereo] || zc <= 0.0) ? 1 : 0;
         a.flags[o] = (uint8_t)f;
         nflag += f;
     }
