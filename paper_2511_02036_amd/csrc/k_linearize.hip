@@ -728,19 +728,35 @@ __global__ __launch_bounds__(kNT) void k_linearize(LinArgs a) {
 #pragma unroll
             for (int i = 0; i < 18; ++i) sm.Z[tid * C::ZS + i] = Zr[i];
             // the observation's own term, D_a = Hpp_a - Z_a Z_a^T and r_a = bp_a - Z_a t, goes
-            // into its camera's sums of this wavefront
+            // into its camera's sums of this wavefront.  Lanes of the same camera belong to
+            // different points; in FP32 chunks a lane adds the 27 entries starting from entry
+            // 0, 9 or 18 (its point's index mod 3), so that fewer lanes of one atomic
+            // instruction meet at the same address (three starts measured faster than two or
+            // four; FP64 chunks have no registers left for the selects)
             Acc *dst = dacc + ((ncopy > 1 ? tid >> 6 : 0) * Kopt + ka) * 27;
-            int e = 0;
+            auto entry = [&](int e) -> Acc {
+                if (e < 21) {
+                    int i = 0;
+                    while ((i + 1) * (i + 2) / 2 <= e) ++i;
+                    const int j = e - i * (i + 1) / 2;
+                    return (Acc)(H[i * 6 + j] - (Zr[i * 3] * Zr[j * 3] + Zr[i * 3 + 1] * Zr[j * 3 + 1] +
+                                                 Zr[i * 3 + 2] * Zr[j * 3 + 2]));
+                }
+                const int i = e - 21;
+                return (Acc)(bpd[i] - ((double)Zr[i * 3] * t0 + (double)Zr[i * 3 + 1] * t1 + (double)Zr[i * 3 + 2] * t2));
+            };
+            if constexpr (sizeof(Real) == 4) {
+                const int cls = pl % 3;
 #pragma unroll
-            for (int i = 0; i < 6; ++i)
+                for (int e = 0; e < 27; ++e) {
+                    const Acc v0 = entry(e), v1 = entry((e + 9) % 27), v2 = entry((e + 18) % 27);
+                    const int o = cls == 0 ? e : cls == 1 ? (e + 9) % 27 : (e + 18) % 27;
+                    lds_add(dst + o, cls == 0 ? v0 : cls == 1 ? v1 : v2);
+                }
+            } else {
 #pragma unroll
-                for (int j = 0; j <= i; ++j, ++e)
-                    lds_add(dst + e, (Acc)(H[i * 6 + j] - (Zr[i * 3] * Zr[j * 3] + Zr[i * 3 + 1] * Zr[j * 3 + 1] +
-                                                              Zr[i * 3 + 2] * Zr[j * 3 + 2])));
-#pragma unroll
-            for (int i = 0; i < 6; ++i)
-                lds_add(dst + 21 + i,
-                        (Acc)(bpd[i] - ((double)Zr[i * 3] * t0 + (double)Zr[i * 3 + 1] * t1 + (double)Zr[i * 3 + 2] * t2)));
+                for (int e = 0; e < 27; ++e) lds_add(dst + e, entry(e));
+            }
         }
 
         // ---- 3. pair lists sorted by camera block --------------------------------------
