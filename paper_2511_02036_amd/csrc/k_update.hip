@@ -26,8 +26,8 @@ struct UpdSmem {
     double *wt;     // 34: 1 / sigma2 per octave (32), Huber thresholds mono, stereo
     int *opt;       // K
     double *dp;     // n
-    double *stgd;   // waves x 64 x 3: q_a
-    double *pslot;  // waves x 64 x 4: per chunk point (dl, denominator part)
+    double *pslot;  // waves x 64 x 4: per chunk observation q_a (3), then per chunk point
+                    // (dl, denominator part): the q_a are read before dl is written
     double *xs;     // waves x 64 x 3: positions of the chunk's points
     int *pst;       // waves x 65: chunk-local first observation of each point
     double *red;    // waves x 3
@@ -40,7 +40,6 @@ static size_t upd_lds_t(int K, int n, int waves, size_t real) {
     o = align_up_u(o + sizeof(double) * (kMaxLevels + 2), 16);
     o = align_up_u(o + sizeof(int) * K, 16);
     o = align_up_u(o + sizeof(double) * (n > 0 ? n : 1), 16);
-    o = align_up_u(o + sizeof(double) * waves * 64 * 3, 16);
     o = align_up_u(o + sizeof(double) * waves * 64 * 4, 16);
     o = align_up_u(o + sizeof(double) * waves * 64 * 3, 16);
     o = align_up_u(o + sizeof(int) * waves * 65, 16);
@@ -67,8 +66,6 @@ __device__ inline UpdSmem<Real> carve_upd(unsigned char *base, int K, int n, int
     o = align_up_u(o + sizeof(int) * K, 16);
     s.dp = reinterpret_cast<double *>(base + o);
     o = align_up_u(o + sizeof(double) * (n > 0 ? n : 1), 16);
-    s.stgd = reinterpret_cast<double *>(base + o);
-    o = align_up_u(o + sizeof(double) * waves * 64 * 3, 16);
     s.pslot = reinterpret_cast<double *>(base + o);
     o = align_up_u(o + sizeof(double) * waves * 64 * 4, 16);
     s.xs = reinterpret_cast<double *>(base + o);
@@ -80,7 +77,8 @@ __device__ inline UpdSmem<Real> carve_upd(unsigned char *base, int K, int n, int
 }
 
 template <typename Real, typename ZT>
-__global__ __launch_bounds__(kUpdThreads) void k_update(UpdArgs a) {
+// six wavefronts per SIMD: 80 VGPRs (no scratch) and about 25 KB of LDS per block
+__global__ __launch_bounds__(kUpdThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_update(UpdArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     // block b: part b % split of tile order[b / split] (the tile's points split evenly)
     const int tt = a.order[blockIdx.x / a.split], sub = blockIdx.x % a.split;
@@ -115,11 +113,12 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(UpdArgs a) {
     }
     __syncthreads();
 
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    double *stgd = sm.stgd + wave * 64 * 3;
+    // (the wavefront index is uniform: its LDS rows are addressed from scalar registers)
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    double *ps = sm.pslot + wave * 64 * 4;
+    double *stgd = ps;   // the chunk's q_a (3 per lane), read before ps is written
     double *xs = sm.xs + wave * 64 * 3;
     int *pst = sm.pst + wave * 65;
-    double *ps = sm.pslot + wave * 64 * 4;
     const int sp0 = tile.p0 + (int)(((int64_t)(tile.p1 - tile.p0) * sub) / a.split);
     const int sp1 = tile.p0 + (int)(((int64_t)(tile.p1 - tile.p0) * (sub + 1)) / a.split);
     const int np = sp1 - sp0;
@@ -160,7 +159,7 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(UpdArgs a) {
         const int o = base + lane;
         int jl = 0, kl = 0, stereo = 0, oct = 0;
         bool act = false;
-        double zu = 0, zv = 0, zr = 0;
+        ZT zu = 0, zv = 0, zr = 0;   // converted where used
         if (o < a.obs.n_obs) {
             jl = a.obs.pt[o];
             kl = a.obs.kf[o];
@@ -170,7 +169,10 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(UpdArgs a) {
             act = (a.mask == nullptr) | (flag == 0);
             stereo = a.obs.type[o];
             oct = a.obs.oct[o];
-            load_z<ZT>(a.obs, o, zu, zv, zr);
+            const ZT *zp = static_cast<const ZT *>(a.obs.z);
+            zu = zp[o];
+            zv = zp[(int64_t)a.obs.n_obs + o];
+            zr = zp[2 * (int64_t)a.obs.n_obs + o];
         }
         wave_sync();
         const int nob = pst[npts];
@@ -205,6 +207,7 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(UpdArgs a) {
         // lane l back-substitutes point p + l with the point factor the linearisation of
         // this step left behind, and publishes dl (points without observations keep their
         // position)
+        double res[4] = {0, 0, 0, 0};
         if (lane < npts && pst[lane + 1] > pst[lane]) {
             const int m0 = pst[lane], m1 = pst[lane + 1];
             double qs[3] = {0, 0, 0};
@@ -224,13 +227,15 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(UpdArgs a) {
             const double d2 = L5 * y2;
             // q^T V^-1 bl = (L^-1 q) . (L^-1 bl)
             const double dq = u0 * t0 + u1 * t1 + u2 * t2;
-            ps[lane * 4 + 0] = d0;
-            ps[lane * 4 + 1] = d1;
-            ps[lane * 4 + 2] = d2;
-            ps[lane * 4 + 3] = d0 * (lambda * d0 + b0) + d1 * (lambda * d1 + b1) + d2 * (lambda * d2 + b2) + dq;
-        } else if (lane < npts) {
+            res[0] = d0;
+            res[1] = d1;
+            res[2] = d2;
+            res[3] = d0 * (lambda * d0 + b0) + d1 * (lambda * d1 + b1) + d2 * (lambda * d2 + b2) + dq;
+        }
+        wave_sync();   // every lane has read the q_a that the results overwrite
+        if (lane < npts) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) ps[lane * 4 + i] = 0.0;
+            for (int i = 0; i < 4; ++i) ps[lane * 4 + i] = res[i];
         }
         wave_sync();
         // one lane per point writes X' and its part of the denominator
@@ -244,7 +249,9 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(UpdArgs a) {
         // trial cost of every active observation at (T', X')
         if (has && act) {
             const int slot = j - p;
-            const double Y0 = X0 + ps[slot * 4], Y1 = X1 + ps[slot * 4 + 1], Y2 = X2 + ps[slot * 4 + 2];
+            // (the position is read again from LDS rather than kept in registers)
+            const double Y0 = xs[3 * slot] + ps[slot * 4], Y1 = xs[3 * slot + 1] + ps[slot * 4 + 1],
+                         Y2 = xs[3 * slot + 2] + ps[slot * 4 + 2];
             double xc, yc, zc, eu, ev, er;
             const double e2 = residual(cam, sm.Tn + kl * 12, Y0, Y1, Y2, zu, zv, zr, stereo, xc, yc, zc, eu, ev, er);
             double rho, w;
