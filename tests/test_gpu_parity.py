@@ -173,6 +173,52 @@ def test_large_tiles_split_across_update_blocks(precision):
         assert_mixed_tolerances(w, g["T"], g["X"], g["stats"][0], r)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_points_seen_once(precision):
+    """Points 200..499 seen by one stereo observation each (the first 200, seen 3-6 times, hold
+    the cameras): the update kernel's chunks then hold 64 points of one observation each, and
+    every lane's point results overwrite observation terms that other lanes read just before
+    (the two share one LDS staging area).  A window of only such points leaves the cameras to
+    the damping alone, too ill-posed for the FP64 bar."""
+    w = synth.tiny_window(40, K=6, n_fixed=2, M=500, nobs=(3, 6), stereo_p=1.0)
+    pt = w["obs_pt"]
+    first = np.r_[True, pt[1:] != pt[:-1]]
+    # (a point seen once in mono is held along its ray by the damping only)
+    keep = (pt < 200) | (first & (w["obs_type"] == 1))
+    w = {k: (v[..., keep] if k.startswith("obs_") else v) for k, v in w.items()}
+    once = np.bincount(w["obs_pt"], minlength=500)[200:]
+    assert (once <= 1).all() and once.sum() > 256
+    print(f"case points seen once precision={precision} N={len(w['obs_pt'])}", flush=True)
+    g = _gpu(w, precision=precision)
+    r = lbaref.solve(w)
+    if precision == "fp64":
+        assert_fp64_parity(w, g["T"], g["X"], g["outlier"], g["stats"][0], r)
+    else:
+        from tests.parity import assert_mixed_tolerances
+        assert_mixed_tolerances(w, g["T"], g["X"], g["stats"][0], r)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_point_with_the_most_observations(precision):
+    """A point with 64 observations, the most one wavefront takes (its first observation
+    repeated): the update kernel's chunk then holds that one point in all 64 lanes, and the
+    linearisation sums its block over 64 observations."""
+    w = synth.tiny_window(32, K=5, n_fixed=2, M=40, nobs=(2, 4), stereo_p=0.5)
+    first = np.flatnonzero(w["obs_pt"] == 0)
+    rep = np.full(64 - len(first), first[0])
+    idx = np.sort(np.concatenate([np.arange(len(w["obs_pt"])), rep]), kind="stable")
+    w = {k: (v[..., idx] if k.startswith("obs_") else v) for k, v in w.items()}
+    assert (w["obs_pt"] == 0).sum() == 64
+    print(f"case point with 64 observations precision={precision} N={len(w['obs_pt'])}", flush=True)
+    g = _gpu(w, precision=precision)
+    r = lbaref.solve(w)
+    if precision == "fp64":
+        assert_fp64_parity(w, g["T"], g["X"], g["outlier"], g["stats"][0], r)
+    else:
+        from tests.parity import assert_mixed_tolerances
+        assert_mixed_tolerances(w, g["T"], g["X"], g["stats"][0], r)
+
+
 def test_size_limits_are_rejected_before_any_solve():
     """61 optimisable keyframes exceed the reduced system's limit of 60 (both
     precisions); a point with 65 observations exceeds one wavefront.  Both are refused
